@@ -1,0 +1,284 @@
+"""Screen-space marching of reflection rays against the depth buffer.
+
+Oracle code (test infrastructure only).
+
+Sec. 3.3 marches a reflection ray r(t) from the pixel's un-projected position
+in screen space and reports an intersection where the ray passes from in
+front of the depth buffer to behind it; Appendix D (Algorithm 1) gives the
+fixed-step version with a depth-match threshold.  Two marches are defined:
+
+* ``march_linear``: the fixed-step march of Algorithm 1.  Readings taken:
+  samples t_k = k * step for k = 1..K (the sample at the origin would hit its
+  own pixel), depth compared in view space, nearest depth texel.  The hit
+  test joins the two statements of the paper: Sec. 3.3 asks for dz to change
+  from negative to positive, Algorithm 1 for |dz| below a threshold.  A
+  sample hits when 0 <= dz <= thickness and an earlier sample had dz < 0
+  (the ray was in front of the depth buffer before it went behind it).
+  Samples inside the origin pixel are skipped and never count as in front.
+
+* ``march_hiz``: the same criterion, made exact for the piecewise-constant
+  depth heightfield and accelerated by a min-depth pyramid (the hierarchical
+  tracing that Sec. 3.3 cites).  The view-space ray is clipped to
+  [0, min(max_dist, near-plane crossing)], projected to a screen segment
+  P(s) = P0 + s (P1 - P0), s in [0, 1], whose depth 1/((1-s)/d0 + s/d1) is
+  monotone in s, and clipped to the screen.  Along the segment the pixels are
+  visited in order; in pixel q the ray's depth runs from d_in to d_out.  The
+  ray hits q when its depth range meets the slab [D[q], D[q] + thickness]
+  and it has been in front of the depth buffer before reaching the slab:
+  either in an earlier pixel (lo < D there) or on entering q (d_in < D[q]).
+  The origin pixel never counts.  The traversal visits cells of the pyramid;
+  each iteration does one of: skip the current level-L cell (whole ray
+  interval in front of its minimum depth) and go up one level, go down one
+  level, or test a level-0 pixel.  ``brute_force_first_hit`` scans every
+  pixel the segment crosses, in order, and is what the traversal must
+  reproduce when the iteration cap is lifted.
+
+Result codes: q >= 0 hit pixel (j*W + i); -1 left the screen or the ray
+segment; -4 iteration cap reached.
+"""
+
+import numpy as np
+
+from . import camera
+
+HIT_OFFSCREEN = -1
+HIT_CAP = -4
+
+
+def hiz_pyramid(depth):
+    """Levels 0..top of the min-depth pyramid (level 0 is the depth itself).
+
+    Level L has ceil(W_{L-1}/2) x ceil(H_{L-1}/2) texels, each the minimum of
+    its (up to four) children; the last level is 1 x 1.
+    """
+    lv = [np.asarray(depth, np.float64)]
+    while lv[-1].shape != (1, 1):
+        d = lv[-1]
+        h, w = d.shape
+        ph, pw = h + (h & 1), w + (w & 1)
+        pad = np.full((ph, pw), np.inf)
+        pad[:h, :w] = d
+        lv.append(pad.reshape(ph // 2, 2, pw // 2, 2).min(axis=(1, 3)))
+    return lv
+
+
+def march_linear(cam, depth, org_pix, V0, Dv, step_len, max_steps, max_dist, thickness):
+    """Fixed-step march (Algorithm 1 with the readings above), vectorised.
+
+    ``org_pix`` [n][2] integer (i, j); ``V0`` [n][3] view-space origins;
+    ``Dv`` [n][3] view-space unit directions.  Returns (codes, iterations).
+    """
+    c = camera.unpack(cam)
+    W, H = c["W"], c["H"]
+    n = V0.shape[0]
+    codes = np.full(n, HIT_CAP, np.int64)
+    iters = np.zeros(n, np.int64)
+    active = np.ones(n, bool)
+    armed = np.zeros(n, bool)
+    K = int(max_steps)
+    if step_len > 0:
+        K = min(K, int(np.floor(max_dist / step_len)))
+    for k in range(1, K + 1):
+        if not active.any():
+            break
+        idx = np.nonzero(active)[0]
+        iters[idx] = k
+        v = V0[idx] + (k * step_len) * Dv[idx]
+        behind = v[:, 2] <= c["z_near"]
+        with np.errstate(divide="ignore", invalid="ignore"):
+            px, py = camera.project(c, v)
+        off = behind | ~(px >= 0) | ~(px < W) | ~(py >= 0) | ~(py < H)
+        codes[idx[off]] = HIT_OFFSCREEN
+        active[idx[off]] = False
+        keep = ~off
+        idx, v, px, py = idx[keep], v[keep], px[keep], py[keep]
+        ix = np.floor(px).astype(np.int64)
+        iy = np.floor(py).astype(np.int64)
+        own = (ix == org_pix[idx, 0]) & (iy == org_pix[idx, 1])
+        dz = v[:, 2] - depth[iy, ix]
+        hit = ~own & armed[idx] & (dz >= 0) & (dz <= thickness)
+        codes[idx[hit]] = iy[hit] * W + ix[hit]
+        active[idx[hit]] = False
+        armed[idx[~own & (dz < 0)]] = True
+    iters[active] = K
+    return codes, iters
+
+
+def screen_segment(cam, org_pix, V0, Dv, max_dist):
+    """Clip the view-space ray and project it: returns P0, dP, d0, d1, s_max, valid.
+
+    P0 is the origin pixel's centre (V0 is its un-projection); the far end is
+    the point at min(max_dist, near-plane crossing).  s_max is where the
+    segment leaves the screen rectangle [0, W] x [0, H] (at most 1).
+    """
+    c = camera.unpack(cam)
+    W, H = c["W"], c["H"]
+    d0 = V0[:, 2]
+    t_end = np.full(V0.shape[0], float(max_dist))
+    with np.errstate(divide="ignore", invalid="ignore"):
+        t_near = (c["z_near"] - d0) / Dv[:, 2]
+    toward = Dv[:, 2] < 0
+    t_end[toward] = np.minimum(t_end[toward], t_near[toward])
+    valid = t_end > 0
+    E = V0 + t_end[:, None] * Dv
+    with np.errstate(divide="ignore", invalid="ignore"):
+        p1x, p1y = camera.project(c, E)
+    P0 = org_pix.astype(np.float64) + 0.5
+    dP = np.stack([p1x, p1y], axis=1) - P0
+    s_max = np.ones(V0.shape[0])
+    with np.errstate(divide="ignore", invalid="ignore"):
+        for ax, lim in ((0, W), (1, H)):
+            sx = np.where(dP[:, ax] > 0, (lim - P0[:, ax]) / dP[:, ax],
+                          np.where(dP[:, ax] < 0, (0.0 - P0[:, ax]) / dP[:, ax], np.inf))
+            s_max = np.minimum(s_max, sx)
+    return P0, dP, d0, E[:, 2], s_max, valid
+
+
+def _ray_depth(d0, d1, s):
+    """Perspective-correct depth along the segment; exactly d0 at s = 0."""
+    with np.errstate(divide="ignore", invalid="ignore"):
+        d = 1.0 / ((1.0 - s) / d0 + s / d1)
+    return np.where(s == 0, d0, d)
+
+
+def march_hiz(cam, pyramid, org_pix, V0, Dv, max_steps, max_dist, thickness):
+    """Hierarchical march over the min pyramid, vectorised in lock step.
+
+    Returns (codes, iterations).  ``max_steps`` caps the iterations (skip,
+    descend and level-0 test each count one).
+    """
+    c = camera.unpack(cam)
+    W, H = c["W"], c["H"]
+    top = len(pyramid) - 1
+    depth = pyramid[0]
+    n = V0.shape[0]
+    P0, dP, d0, d1, s_max, valid = screen_segment(cam, org_pix, V0, Dv, max_dist)
+    codes = np.full(n, HIT_CAP, np.int64)
+    iters = np.zeros(n, np.int64)
+    codes[~valid] = HIT_OFFSCREEN
+    active = valid.copy()
+    s = np.zeros(n)
+    armed = np.zeros(n, bool)
+    L = np.zeros(n, np.int64)
+    ix = org_pix[:, 0].astype(np.int64).copy()
+    iy = org_pix[:, 1].astype(np.int64).copy()
+    step = 0
+    while active.any() and step < max_steps:
+        step += 1
+        a = np.nonzero(active)[0]
+        iters[a] += 1
+        La = L[a]
+        size = np.left_shift(1, La)
+        cx0 = (ix[a] >> La) * size
+        cy0 = (iy[a] >> La) * size
+        cx1 = np.minimum(cx0 + size, W)
+        cy1 = np.minimum(cy0 + size, H)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            sx = np.where(dP[a, 0] > 0, (cx1 - P0[a, 0]) / dP[a, 0],
+                          np.where(dP[a, 0] < 0, (cx0 - P0[a, 0]) / dP[a, 0], np.inf))
+            sy = np.where(dP[a, 1] > 0, (cy1 - P0[a, 1]) / dP[a, 1],
+                          np.where(dP[a, 1] < 0, (cy0 - P0[a, 1]) / dP[a, 1], np.inf))
+        s_exit = np.minimum(np.minimum(sx, sy), s_max[a])
+        din = _ray_depth(d0[a], d1[a], s[a])
+        dout = _ray_depth(d0[a], d1[a], s_exit)
+        hi = np.maximum(din, dout)
+        lo = np.minimum(din, dout)
+        zc = _gather(pyramid, La, ix[a], iy[a])
+        skip = hi < zc
+        level0 = ~skip & (La == 0)
+        descend = ~skip & (La > 0)
+        own = level0 & (ix[a] == org_pix[a, 0]) & (iy[a] == org_pix[a, 1])
+        test = level0 & ~own
+        dq = depth[iy[a], ix[a]]
+        hit = test & (lo <= dq + thickness) & (armed[a] | (din < dq))
+        advance = skip | own | (test & ~hit)
+        # the ray was in front of the depth buffer somewhere in a skipped cell
+        # or in a tested pixel it passes
+        armed[a[(skip & (s_exit > s[a])) | (test & (lo < dq))]] = True
+        # hits
+        ah = a[hit]
+        codes[ah] = iy[ah] * W + ix[ah]
+        active[ah] = False
+        # descents
+        L[a[descend]] -= 1
+        # advances: leave at the segment end, else step into the next cell
+        ends = advance & (s_exit >= s_max[a])
+        codes[a[ends]] = HIT_OFFSCREEN
+        active[a[ends]] = False
+        mv = advance & ~ends
+        am = a[mv]
+        se = s_exit[mv]
+        crx = sx[mv] == se
+        cry = sy[mv] == se
+        px = P0[am, 0] + se * dP[am, 0]
+        py = P0[am, 1] + se * dP[am, 1]
+        nx = np.where(crx, np.where(dP[am, 0] > 0, cx1[mv], cx0[mv] - 1),
+                      np.clip(np.floor(px).astype(np.int64), cx0[mv], cx1[mv] - 1))
+        ny = np.where(cry, np.where(dP[am, 1] > 0, cy1[mv], cy0[mv] - 1),
+                      np.clip(np.floor(py).astype(np.int64), cy0[mv], cy1[mv] - 1))
+        ix[am] = nx
+        iy[am] = ny
+        s[am] = se
+        L[am] = np.minimum(L[am] + 1, top)
+        # a step past the screen edge (boundary coinciding with it) leaves too
+        gone = (nx < 0) | (nx >= W) | (ny < 0) | (ny >= H)
+        codes[am[gone]] = HIT_OFFSCREEN
+        active[am[gone]] = False
+    return codes, iters
+
+
+def _gather(pyramid, L, ix, iy):
+    out = np.empty(L.shape[0])
+    for lv in np.unique(L):
+        sel = L == lv
+        out[sel] = pyramid[lv][iy[sel] >> lv, ix[sel] >> lv]
+    return out
+
+
+def brute_force_first_hit(cam, depth, org_pix, V0, Dv, max_dist, thickness):
+    """First hit by scanning every pixel the segment crosses (tiny images only).
+
+    For each pixel box [i, i+1] x [j, j+1] the s-interval of the clipped
+    screen segment inside it is found by slab clipping, without any pyramid.
+    The crossed pixels (positive-length intervals, origin excluded) are then
+    walked in order of entry; the ray's depth over a pixel's interval
+    (monotone in s) is compared with the slab [D, D + thickness] under the
+    in-front-first rule.  Returns codes.
+    """
+    c = camera.unpack(cam)
+    W, H = c["W"], c["H"]
+    P0, dP, d0, d1, s_max, valid = screen_segment(cam, org_pix, V0, Dv, max_dist)
+    n = V0.shape[0]
+    out = np.full(n, HIT_OFFSCREEN, np.int64)
+    jj, ii = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
+    ii = ii.reshape(-1)
+    jj = jj.reshape(-1)
+    D = np.asarray(depth, np.float64).reshape(-1)
+    for r in range(n):
+        if not valid[r]:
+            continue
+        lo_s = np.zeros(ii.shape)
+        hi_s = np.full(ii.shape, s_max[r])
+        for ax, cell in ((0, ii), (1, jj)):
+            if dP[r, ax] == 0:
+                inside = (cell <= P0[r, ax]) & (P0[r, ax] < cell + 1)
+                hi_s = np.where(inside, hi_s, -np.inf)
+                continue
+            sa = (cell - P0[r, ax]) / dP[r, ax]
+            sb = (cell + 1 - P0[r, ax]) / dP[r, ax]
+            lo_s = np.maximum(lo_s, np.minimum(sa, sb))
+            hi_s = np.minimum(hi_s, np.maximum(sa, sb))
+        crossed = hi_s > lo_s
+        crossed &= ~((ii == org_pix[r, 0]) & (jj == org_pix[r, 1]))
+        order = np.nonzero(crossed)[0]
+        order = order[np.argsort(lo_s[order], kind="stable")]
+        armed = False
+        for k in order:
+            din = _ray_depth(d0[r], d1[r], lo_s[k])
+            dout = _ray_depth(d0[r], d1[r], hi_s[k])
+            lo, hi = min(din, dout), max(din, dout)
+            if hi >= D[k] and lo <= D[k] + thickness and (armed or din < D[k]):
+                out[r] = jj[k] * W + ii[k]
+                break
+            armed = armed or lo < D[k]
+    return out

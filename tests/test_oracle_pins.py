@@ -1,0 +1,478 @@
+"""Pins of the FP64 oracle against things other than itself.
+
+Each test ties one part of the oracle to a published value, a library
+routine, a closed form, an invariant or brute force, chosen so that a
+plausible slip (a dropped term, a wrong sign or index, a swapped operand)
+fails at least one of them.  CPU only.
+"""
+
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import brdf, camera, env, march, philox, shade
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------- Philox ---
+
+def _kat():
+    rows = []
+    with open(os.path.join(GOLDEN, "philox4x32_10_kat.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            w = [int(x, 16) for x in line.split()]
+            rows.append((w[0:4], w[4:6], w[6:10]))
+    return rows
+
+
+def test_philox4x32_known_answers():
+    """Published Random123 known-answer vectors for Philox4x32-10."""
+    for ctr, key, want in _kat():
+        assert philox.philox([ctr], [key], bits=32).tolist() == [want]
+        assert philox.philox4x32(np.array([ctr]), np.array(key)).tolist() == [want]
+
+
+def test_philox_structure_matches_numpy_4x64():
+    """The generic round/key schedule, instantiated at 64 bits, reproduces
+    NumPy's independent Philox4x64-10 stream (counter incremented before use)."""
+    ctr = np.array([11, 22, 33, 44], dtype=np.uint64)
+    key = np.array([0x1234567890ABCDEF, 0xFEDCBA0987654321], dtype=np.uint64)
+    g = np.random.Philox(counter=ctr, key=key)
+    raw = g.random_raw(12).reshape(3, 4)
+    mine = philox.philox([[12 + k, 22, 33, 44] for k in range(3)], [key.tolist()], bits=64)
+    assert np.array_equal(raw, mine)
+
+
+def test_philox_vectorised_equals_exact():
+    rng = np.random.default_rng(5)
+    c = rng.integers(0, 2 ** 32, (500, 4), dtype=np.uint64)
+    k = rng.integers(0, 2 ** 32, (500, 2), dtype=np.uint64)
+    assert np.array_equal(philox.philox(c, k), philox.philox4x32(c, k))
+
+
+def test_uniforms_exact_grid_and_uniform():
+    n = 200_000
+    u1, u2 = philox.sample_uniforms(np.arange(n), 3, 0, 0x1234_5678_9ABC)
+    for u in (u1, u2):
+        assert u.min() >= 0.0 and u.max() < 1.0
+        assert np.all(u * 2 ** 24 == np.floor(u * 2 ** 24))           # multiples of 2^-24
+        assert np.all(u.astype(np.float32).astype(np.float64) == u)   # exact in f32
+        counts = np.bincount((u * 64).astype(int), minlength=64)
+        chi2 = ((counts - n / 64) ** 2 / (n / 64)).sum()
+        assert chi2 < 120  # 63 dof: p ~ 1e-5
+    assert abs(np.corrcoef(u1, u2)[0, 1]) < 0.01
+    assert abs(np.corrcoef(u1[:-1], u1[1:])[0, 1]) < 0.01
+    # a different sample index or frame gives a different stream
+    v1, _ = philox.sample_uniforms(np.arange(1000), 4, 0, 0x1234_5678_9ABC)
+    w1, _ = philox.sample_uniforms(np.arange(1000), 3, 1, 0x1234_5678_9ABC)
+    assert not np.array_equal(u1[:1000], v1) and not np.array_equal(u1[:1000], w1)
+
+
+# ------------------------------------------------------------ ONB / BRDF ---
+
+def test_onb_orthonormal_right_handed():
+    rng = np.random.default_rng(1)
+    n = brdf.normalize(rng.normal(size=(2000, 3)))
+    n = np.concatenate([n, [[0, 0, 1.0], [0, 0, -1.0], [1.0, 0, 0.0], [0.0, 1.0, 0.0],
+                            [1.0, 0.0, -0.0], [0.6, 0.8, 0.0]]])
+    t, b = brdf.onb(n)
+    for u, v in ((t, b), (t, n), (b, n)):
+        assert np.abs(brdf.dot(u, v)).max() < 1e-12
+    for u in (t, b):
+        assert np.abs(np.linalg.norm(u, axis=1) - 1).max() < 1e-12
+    assert np.abs(np.cross(t, b) - n).max() < 1e-12
+    # sign(+0) = +1 and sign(-0) = -1 both give a valid frame
+    t0, b0 = brdf.onb(np.array([[0.6, 0.8, 0.0]]))
+    assert np.allclose(t0, [[1 - 0.36, -0.48, -0.6]])
+
+
+def _random_setup(rng, m, alpha=None):
+    cos_no = rng.uniform(0.05, 1.0, m)
+    wo = np.stack([np.sqrt(1 - cos_no ** 2), np.zeros(m), cos_no], axis=1)
+    a = rng.uniform(0.05, 1.0, m) if alpha is None else np.full(m, alpha)
+    return wo, a
+
+
+def test_vndf_mirror_is_exact():
+    """rho = 0: the visible-normal sample is the normal itself, for any u."""
+    rng = np.random.default_rng(2)
+    wo, _ = _random_setup(rng, 1000)
+    h = brdf.sample_vndf(wo, np.zeros(1000), rng.uniform(0, 1, 1000), rng.uniform(0, 1 - 2 ** -24, 1000))
+    assert np.array_equal(h, np.tile([0.0, 0.0, 1.0], (1000, 1)))
+
+
+def test_weights_bounded_and_long_equals_short():
+    rng = np.random.default_rng(3)
+    m = 1_000_000
+    wo, a = _random_setup(rng, m)
+    u1, u2 = rng.uniform(0, 1, m), rng.uniform(0, 1, m)
+    h = brdf.sample_vndf(wo, a, u1, u2)
+    assert np.all(h[:, 2] > 0)
+    cos_oh = brdf.dot(wo, h)
+    assert np.all(cos_oh > 0)                      # visible normals only
+    l = 2 * cos_oh[:, None] * h - wo
+    cos_nl = l[:, 2]
+    ok = cos_nl > 0
+    f0 = rng.uniform(0, 1, (m, 3))
+    ws = brdf.weight_short(f0[ok], cos_oh[ok], cos_nl[ok], a[ok])
+    assert ws.max() <= 1.0 + 1e-15 and ws.min() >= 0.0
+    sub = np.nonzero(ok)[0][:200_000]
+    wl = brdf.weight_long(f0[sub], wo[sub, 2], cos_nl[sub], cos_oh[sub], h[sub, 2], a[sub])
+    wsub = brdf.weight_short(f0[sub], cos_oh[sub], cos_nl[sub], a[sub])
+    assert np.abs(wl - wsub).max() <= 1e-12
+
+
+@pytest.mark.parametrize("alpha,cos_no", [(0.3, 0.9), (0.6, 0.5), (1.0, 0.2), (0.45, 0.15)])
+@pytest.mark.parametrize("f0", [1.0, 0.0, 0.04])
+def test_vndf_mean_weight_matches_quadrature(alpha, cos_no, f0):
+    """E[w] under the sampler equals the integral of f_s cos over the
+    hemisphere by quadrature, which uses only the closed-form D, F and G.
+    F0 = 1 weighs by G1 alone, F0 = 0 by the Fresnel tail, so a wrong
+    sampling density fails one of them."""
+    rng = np.random.default_rng(int(alpha * 1000 + cos_no * 100 + f0 * 7))
+    m = 400_000
+    wo = np.tile([math.sqrt(1 - cos_no ** 2), 0.0, cos_no], (m, 1))
+    h = brdf.sample_vndf(wo, np.full(m, alpha), rng.uniform(0, 1, m), rng.uniform(0, 1, m))
+    cos_oh = brdf.dot(wo, h)
+    l = 2 * cos_oh[:, None] * h - wo
+    w = np.zeros(m)
+    ok = l[:, 2] > 0
+    w[ok] = brdf.weight_short(np.full((ok.sum(), 1), f0), cos_oh[ok], l[ok, 2], np.full(ok.sum(), alpha))[:, 0]
+    mc, se = w.mean(), w.std() / math.sqrt(m)
+    quad = brdf.specular_albedo_quadrature(np.array([f0]), cos_no, alpha, 1200, 600)[0]
+    assert abs(mc - quad) < 4 * se + 2e-4 * max(quad, 1e-3), (mc, quad, se)
+
+
+def test_vndf_below_surface_fraction_matches_pdf():
+    """P(n.l > 0) from the sampler equals the integral of the closed-form
+    reflected visible-normal density over the upper hemisphere."""
+    alpha, cos_no = 0.8, 0.3
+    rng = np.random.default_rng(11)
+    m = 400_000
+    wo = np.tile([math.sqrt(1 - cos_no ** 2), 0.0, cos_no], (m, 1))
+    h = brdf.sample_vndf(wo, np.full(m, alpha), rng.uniform(0, 1, m), rng.uniform(0, 1, m))
+    cos_oh = brdf.dot(wo, h)
+    frac = ((2 * cos_oh[:, None] * h - wo)[:, 2] > 0).mean()
+    nt, npd = 1200, 600
+    mu = (np.arange(nt) + 0.5) / nt
+    ph = (np.arange(npd) + 0.5) / npd * 2 * math.pi
+    MU, PH = np.meshgrid(mu, ph, indexing="ij")
+    s = np.sqrt(1 - MU ** 2)
+    wi = np.stack([s * np.cos(PH), s * np.sin(PH), MU], -1)
+    hh = brdf.normalize(wi + wo[0])
+    pdf = brdf.vndf_pdf_l(cos_no, brdf.dot(hh, wo[0]), hh[..., 2], alpha)
+    integral = pdf.sum() / nt * 2 * math.pi / npd
+    assert abs(frac - integral) < 4 * math.sqrt(frac * (1 - frac) / m) + 1e-3
+
+
+def test_microfacet_closed_forms():
+    # D integrates to one over projected area: int D(h) (h.n) dh = 1
+    for alpha in (0.2, 0.5, 1.0):
+        mu = (np.arange(20000) + 0.5) / 20000
+        assert abs((brdf.ndf(mu, alpha) * mu).sum() / 20000 * 2 * math.pi - 1) < 1e-3
+    # alpha = 1: D = 1/pi, G1(z) = 2z / (1 + z); alpha = 0: G1 = 1
+    assert np.allclose(brdf.ndf(np.linspace(0, 1, 9), 1.0), 1 / math.pi)
+    z = np.linspace(0.01, 1, 9)
+    assert np.allclose(brdf.smith_g1(z, 1.0), 2 * z / (1 + z))
+    assert np.allclose(brdf.smith_g1(z, 0.0), 1.0)
+    # Schlick: F(1) = F0, F(0) = 1, textbook (1 - c)^5 form
+    f0 = np.array([[0.04, 0.5, 1.0]])
+    assert np.allclose(brdf.schlick(f0, np.array([1.0])), f0)
+    assert np.allclose(brdf.schlick(f0, np.array([0.0])), 1.0)
+    assert np.allclose(brdf.schlick(np.array([[0.0]]), np.array([0.5])), 0.5 ** 5)
+
+
+# ------------------------------------------------------------------- env ---
+
+def test_env_uv_closed_forms():
+    d = np.array([[0, 0, -1.0], [1.0, 0, 0], [0, 0, 1.0], [-1.0, 0, 0], [0, 1.0, 0], [0, -1.0, 0]])
+    u, v = env.dir_to_uv(d)
+    assert np.allclose(u[:4], [0.5, 0.75, 1.0, 0.25]) and np.allclose(v[:4], 0.5)
+    assert v[4] == 0.0 and v[5] == 1.0
+
+
+def test_env_bilinear_texel_centres_and_uniform():
+    rng = np.random.default_rng(4)
+    he, we = 8, 16
+    img = rng.uniform(0.5, 2, (he, we, 3))
+    for y in range(he):
+        for x in range(we):
+            u = (x + 0.5) / we
+            v = (y + 0.5) / he
+            phi = (u - 0.5) * 2 * math.pi
+            th = v * math.pi
+            d = np.array([[math.sin(th) * math.sin(phi), math.cos(th), -math.sin(th) * math.cos(phi)]])
+            assert np.allclose(env.bilinear(img, d)[0], img[y, x], rtol=1e-12)
+    # wrap: halfway between the last and first column
+    th = 0.5 * math.pi * (2 * 3 + 1) / he * 2 / 2
+    v = (3 + 0.5) / he
+    th = v * math.pi
+    d = np.array([[math.sin(th) * math.sin(-math.pi), math.cos(th), -math.sin(th) * math.cos(-math.pi)]])
+    assert np.allclose(env.bilinear(img, d)[0], 0.5 * (img[3, 0] + img[3, we - 1]), rtol=1e-12)
+    # constant map: every filter returns the constant
+    const = np.full((he, we, 3), 3.25)
+    mips = env.build_mips(const)
+    dd = brdf.normalize(rng.normal(size=(1000, 3)))
+    assert np.abs(env.bilinear(const, dd) - 3.25).max() < 1e-14
+    assert np.abs(env.trilinear(mips, dd, rng.uniform(0, 3, 1000)) - 3.25).max() < 1e-14
+
+
+def test_env_mips_are_block_means():
+    rng = np.random.default_rng(6)
+    img = np.exp(rng.normal(0, 2, (32, 64, 3)))
+    mips = env.build_mips(img)
+    assert len(mips) == 6 and mips[-1].shape == (1, 2, 3)
+    for k, m in enumerate(mips):
+        b = 2 ** k
+        direct = np.array([[img[y * b:(y + 1) * b, x * b:(x + 1) * b].reshape(-1, 3).mean(0)
+                            for x in range(64 // b)] for y in range(32 // b)])
+        assert np.allclose(m, direct, rtol=1e-13)
+    assert env.roughness_level(mips, 1.0) == 5.0 and env.roughness_level(mips, 0.0) == 0.0
+
+
+# --------------------------------------------------------------- pyramid ---
+
+@pytest.mark.parametrize("h,w", [(1, 1), (1, 7), (5, 3), (9, 13), (16, 16), (33, 17)])
+def test_hiz_pyramid_is_block_min(h, w):
+    rng = np.random.default_rng(h * 100 + w)
+    d = rng.uniform(1, 10, (h, w))
+    d[rng.uniform(size=(h, w)) < 0.2] = np.inf
+    lv = march.hiz_pyramid(d)
+    assert lv[-1].shape == (1, 1)
+    for L, img in enumerate(lv):
+        b = 2 ** L
+        assert img.shape == (-(-h // b), -(-w // b))
+        for y in range(img.shape[0]):
+            for x in range(img.shape[1]):
+                assert img[y, x] == d[y * b:(y + 1) * b, x * b:(x + 1) * b].min()
+
+
+# ----------------------------------------------------------------- march ---
+
+def _tiny_camera(w, h):
+    return dict(width=w, height=h, pos=np.zeros(3), rot=np.eye(3), fx=w * 0.9, fy=w * 0.9,
+                cx=w / 2, cy=h / 2, z_near=0.01)
+
+
+def _random_rays(rng, cam, depth, m):
+    c = camera.unpack(cam)
+    h, w = depth.shape
+    fin = np.argwhere(np.isfinite(depth))
+    pick = fin[rng.integers(0, fin.shape[0], m)]
+    org = np.stack([pick[:, 1], pick[:, 0]], 1)
+    V0 = camera.pixel_view_point(c, org[:, 0].astype(float), org[:, 1].astype(float),
+                                 depth[pick[:, 0], pick[:, 1]])
+    Dv = brdf.normalize(rng.normal(size=(m, 3)))
+    return org, V0, Dv
+
+
+@pytest.mark.parametrize("h,w", [(4, 4), (9, 13), (16, 16), (21, 7), (32, 32)])
+def test_hiz_march_equals_brute_force(h, w):
+    """Cap lifted, the pyramid traversal finds exactly the first hit of the
+    pixel-by-pixel scan; with the cap on, rays that need at most the cap
+    agree too and the rest report -4."""
+    rng = np.random.default_rng(h * 31 + w)
+    cam = _tiny_camera(w, h)
+    ok_rays = 0
+    for trial in range(6):
+        depth = rng.uniform(1.0, 3.0, (h, w))
+        if trial % 2:
+            depth[rng.uniform(size=(h, w)) < 0.3] = np.inf
+        if trial == 4:  # a smooth slanted surface: exercises the in-front-first rule
+            jj, ii = np.meshgrid(np.arange(h), np.arange(w), indexing="ij")
+            depth = 1.5 + 0.08 * jj + 0.03 * ii
+        org, V0, Dv = _random_rays(rng, cam, depth, 150)
+        pyr = march.hiz_pyramid(depth)
+        for thick in (0.05, 0.5):
+            want = march.brute_force_first_hit(cam, depth, org, V0, Dv, 6.0, thick)
+            got, it = march.march_hiz(cam, pyr, org, V0, Dv, 10 ** 6, 6.0, thick)
+            assert np.array_equal(got, want)
+            capped, itc = march.march_hiz(cam, pyr, org, V0, Dv, 12, 6.0, thick)
+            within = it <= 12
+            assert np.array_equal(capped[within], want[within])
+            assert np.all(capped[~within] == march.HIT_CAP)
+            assert np.all(itc <= 12)
+            ok_rays += within.sum()
+    assert ok_rays > 0
+
+
+def test_linear_march_wall_closed_form():
+    """A ray from depth 2 toward a fronto-parallel wall at depth 5: it is in
+    front at the first sample, then hits at sample k* = ceil(3/(step*dz))
+    exactly when that sample lies inside the slab, in the pixel it projects to."""
+    w = h = 64
+    cam = _tiny_camera(w, h)
+    c = camera.unpack(cam)
+    depth = np.full((h, w), 5.0)
+    rng = np.random.default_rng(8)
+    n_checked = 0
+    for _ in range(400):
+        i, j = rng.integers(8, 56, 2)
+        depth_o = 2.0
+        V0 = camera.pixel_view_point(c, np.array([float(i)]), np.array([float(j)]), np.array([depth_o]))
+        Dv = brdf.normalize(np.array([[rng.uniform(-0.3, 0.3), rng.uniform(-0.3, 0.3), 1.0]]))
+        step = 0.125
+        thick = 0.05
+        kstar = math.ceil(3.0 / (step * Dv[0, 2]))
+        zk = depth_o + kstar * step * Dv[0, 2]
+        p = V0[0] + kstar * step * Dv[0]
+        px, py = c["cx"] + c["fx"] * p[0] / p[2], c["cy"] - c["fy"] * p[1] / p[2]
+        if not (0 <= px < w and 0 <= py < h) or kstar > 32:
+            continue
+        # first sample must leave the origin pixel for the ray to be "in front"
+        p1 = V0[0] + step * Dv[0]
+        if (math.floor(c["cx"] + c["fx"] * p1[0] / p1[2]), math.floor(c["cy"] - c["fy"] * p1[1] / p1[2])) == (i, j):
+            continue
+        want = int(math.floor(py)) * w + int(math.floor(px)) if zk - 5.0 <= thick else march.HIT_CAP
+        if want == march.HIT_CAP and kstar < 32:
+            continue  # it would go on marching behind the wall until the cap; checked below
+        got, it = march.march_linear(cam, depth, np.array([[i, j]]), V0, Dv, step, 32, 4.0, thick)
+        assert got[0] == want and it[0] == kstar
+        n_checked += 1
+    assert n_checked > 50
+
+
+# -------------------------------------------------- closed-form scenes ---
+
+def _floor_wall_scene(w=64, h=64, wall_z=-6.0, cam_h=1.0):
+    """Camera at height cam_h looking along -z at a mirror floor y=0 and a
+    fronto-parallel wall z=wall_z.  G-buffers by exact ray casting here."""
+    cam = dict(width=w, height=h, pos=np.array([0.0, cam_h, 0.0]),
+               rot=np.array([[1.0, 0, 0], [0, 1.0, 0], [0, 0, -1.0]]),
+               fx=w * 0.8, fy=w * 0.8, cx=w / 2, cy=h / 2, z_near=0.01)
+    c = camera.unpack(cam)
+    jj, ii = np.meshgrid(np.arange(h, dtype=float), np.arange(w, dtype=float), indexing="ij")
+    x = (ii + 0.5 - c["cx"]) / c["fx"]
+    y = -(jj + 0.5 - c["cy"]) / c["fy"]
+    t_floor = np.where(y < 0, -cam_h / np.where(y < 0, y, -1), np.inf)
+    t_wall = -wall_z
+    is_floor = t_floor < t_wall
+    depth = np.where(is_floor, t_floor, t_wall)
+    nr = np.zeros((h, w, 4))
+    am = np.zeros((h, w, 4))
+    nr[is_floor] = [0, 1, 0, 0.0]            # mirror floor
+    am[is_floor] = [1, 1, 1, 1.0]
+    nr[~is_floor] = [0, 0, 1, 0.7]           # rough dielectric wall
+    am[~is_floor] = [0.5, 0.5, 0.5, 0.0]
+    rad = np.zeros((h, w, 4))
+    rad[..., 0] = np.arange(h * w).reshape(h, w) + 1.0   # identifies the pixel
+    rad[..., 1] = 1.0
+    rad[..., 2] = 2.0
+    return cam, dict(depth=depth, normal_rough=nr, albedo_metal=am, radiance=rad), is_floor
+
+
+def test_mirror_floor_hits_wall_at_closed_form_pixel():
+    cam, g, is_floor = _floor_wall_scene()
+    c = camera.unpack(cam)
+    W, H = c["W"], c["H"]
+    envmap = np.full((8, 16, 3), 0.25)
+    params = dict(spp=1, march=1, max_steps=10 ** 6, step_len=0.125, max_dist=100.0,
+                  thickness=0.05, seed=7, frame=0, flags=shade.NO_DIRECT)
+    pix = np.nonzero(is_floor.reshape(-1))[0]
+    r = shade.shade_pixels(cam, g, envmap, params, pix)
+    checked = 0
+    for k, q in enumerate(pix):
+        i, j = q % W, q // W
+        D = g["depth"][j, i]
+        p = c["pos"] + camera.view_to_world_dir(c, camera.pixel_view_point(c, np.array(i, float), np.array(j, float), np.array(D)))
+        wo = (c["pos"] - p) / np.linalg.norm(c["pos"] - p)
+        l = np.array([-wo[0], wo[1], -wo[2]])          # mirror about +y
+        t = (p[2] + 6.0) / (-l[2])
+        x = p + t * l
+        v = x - c["pos"]
+        px = c["cx"] + c["fx"] * v[0] / (-v[2])
+        py = c["cy"] - c["fy"] * v[1] / (-v[2])
+        if not (0 <= px < W and 0 <= py < H):
+            assert r["hits"][k, 0] == march.HIT_OFFSCREEN
+            assert np.allclose(r["out"][k], 0.25)       # miss reads the env
+            continue
+        if min(px - math.floor(px), math.ceil(px) - px, py - math.floor(py), math.ceil(py) - py) < 1e-6:
+            continue
+        want = int(py) * W + int(px)
+        assert r["hits"][k, 0] == want
+        # F0 = 1 and G1 = 1 for a perfect mirror: the output is the hit's radiance
+        assert np.allclose(r["out"][k], g["radiance"].reshape(-1, 4)[want, :3], rtol=1e-13)
+        checked += 1
+    assert checked > 300
+
+
+def _open_floor(w=48, h=32, rough=0.0, metal=1.0, albedo=1.0):
+    """Camera looking down at an unbounded floor and nothing else."""
+    cam = dict(width=w, height=h, pos=np.array([0.0, 3.0, 0.0]),
+               rot=np.array([[1.0, 0, 0], [0, 0, -1.0], [0, -1.0, 0]]),
+               fx=w * 0.6, fy=w * 0.6, cx=w / 2, cy=h / 2, z_near=0.01)
+    depth = np.full((h, w), 3.0)
+    nr = np.tile([0, 1.0, 0, rough], (h, w, 1))
+    am = np.tile([albedo, albedo, albedo, metal], (h, w, 1))
+    rad = np.tile([5.0, 6.0, 7.0, 0], (h, w, 1))
+    return cam, dict(depth=depth, normal_rough=nr, albedo_metal=am, radiance=rad)
+
+
+def test_white_furnace():
+    """Uniform environment L, specular off, dielectric: out = a * L exactly."""
+    L = 1.75
+    cam, g = _open_floor(metal=0.0, rough=0.4)
+    rng = np.random.default_rng(9)
+    g["albedo_metal"][..., :3] = rng.uniform(0, 1, g["albedo_metal"][..., :3].shape)
+    g["normal_rough"][..., 3] = rng.uniform(0, 1, g["normal_rough"][..., 3].shape)
+    tilt = brdf.normalize(rng.normal(size=(32, 48, 3)) * 0.2 + [0, 1, 0])
+    g["normal_rough"][..., :3] = tilt
+    envmap = np.full((16, 32, 3), L)
+    params = dict(spp=4, march=1, max_steps=64, step_len=0.125, max_dist=100.0,
+                  thickness=0.05, seed=1, frame=0, flags=shade.NO_SPECULAR)
+    r = shade.shade_frame(cam, g, envmap, params)
+    assert np.abs(r["out"] - g["albedo_metal"][..., :3] * L).max() < 1e-14
+    assert np.all(r["hits"] == shade.HIT_SKIPPED)
+
+
+def test_mirror_furnace():
+    """Perfect mirror (a = 1, m = 1, rho = 0) over an open floor under a
+    uniform environment: every ray leaves the screen and out = L exactly."""
+    L = 2.5
+    cam, g = _open_floor()
+    envmap = np.full((16, 32, 3), L)
+    params = dict(spp=2, march=1, max_steps=64, step_len=0.125, max_dist=100.0,
+                  thickness=0.05, seed=3, frame=0, flags=0)
+    r = shade.shade_frame(cam, g, envmap, params)
+    assert np.all(r["hits"] == march.HIT_OFFSCREEN)
+    assert np.abs(r["out"] - L).max() < 1e-14
+
+
+def test_rough_furnace_equals_directional_albedo():
+    """Rough metal under a uniform environment with nothing to hit: the
+    pixel mean over many samples converges to L * int f_s cos (quadrature)."""
+    L = 1.0
+    alpha = 0.5
+    cam, g = _open_floor(w=8, h=8, rough=alpha, metal=1.0, albedo=0.8)
+    envmap = np.full((16, 32, 3), L)
+    params = dict(spp=4096, march=1, max_steps=64, step_len=0.125, max_dist=100.0,
+                  thickness=0.05, seed=12, frame=0, flags=0)
+    W = 8
+    q = 3 * W + 5
+    r = shade.shade_pixels(cam, g, envmap, params, np.array([q]))
+    c = camera.unpack(cam)
+    p = c["pos"] + camera.view_to_world_dir(c, camera.pixel_view_point(c, np.array(5.0), np.array(3.0), np.array(3.0)))
+    cos_no = (c["pos"] - p)[1] / np.linalg.norm(c["pos"] - p)
+    quad = brdf.specular_albedo_quadrature(np.array([0.8]), cos_no, alpha, 1200, 600)[0]
+    assert np.all(r["hits"] < 0)
+    assert abs(r["out"][0, 0] - quad) < 0.02 * quad
+
+
+def test_background_reads_environment():
+    cam, g = _open_floor(w=8, h=8)
+    g["depth"][:] = np.inf
+    rng = np.random.default_rng(2)
+    envmap = rng.uniform(1, 2, (8, 16, 3))
+    params = dict(spp=1, march=0, max_steps=32, step_len=0.125, max_dist=4.0,
+                  thickness=0.05, seed=0, frame=0, flags=0)
+    r = shade.shade_frame(cam, g, envmap, params)
+    c = camera.unpack(cam)
+    jj, ii = np.meshgrid(np.arange(8), np.arange(8), indexing="ij")
+    d = camera.view_ray_dir(c, ii.reshape(-1), jj.reshape(-1))
+    assert np.allclose(r["out"].reshape(-1, 3), env.bilinear(envmap, d), rtol=1e-14)
+    assert np.all(r["hits"] == shade.HIT_BACKGROUND)
