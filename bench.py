@@ -1,0 +1,249 @@
+"""Throughput of screen-space GGX shading on one MI355X.
+
+One step = one frame of the whole hot path on the headline workload: build
+the min-depth pyramid of the frame's depth buffer, then shade every pixel
+(direct diffuse + 16-sample Monte-Carlo specular with the hierarchical
+march) of the 1920x1080 synthetic scene (ground plane, 40 spheres, 60 boxes,
+512x256 lognormal(0, 2) environment; the paper's own data is not public).
+Inputs are resident in HBM before timing; the env mip chain is built once
+(the environment is an input that does not change between frames).
+
+Prints one JSON line: Mrays/s (= W*H*spp / frame time), ms per frame, the
+FP16 and BF16 G-buffer variants of the same frame, the roofline figure of the
+shading kernel and the FP64 oracle timed on this host's cores.
+"""
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", default="c2")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true", help="FP32 only")
+    ap.add_argument("--cpu-rows", type=int, default=0,
+                    help="oracle sample: every k-th row (default 8)")
+    return ap.parse_args()
+
+
+def upload(scene, dtype, dev):
+    import torch
+
+    from scenes import quantise_gbuffer
+    t = dict(depth=torch.from_numpy(scene.depth).to(dev), env=torch.from_numpy(scene.env).to(dev))
+    if dtype == "f32":
+        for k in ("normal_rough", "albedo_metal", "radiance"):
+            t[k] = torch.from_numpy(getattr(scene, k)).to(dev)
+    else:
+        bits, _ = quantise_gbuffer(scene, dtype)
+        tdt = torch.float16 if dtype == "f16" else torch.bfloat16
+        for k in ("normal_rough", "albedo_metal", "radiance"):
+            t[k] = torch.from_numpy(bits[k].view(np.int16)).to(dev).view(tdt)
+    return t
+
+
+def algorithmic_bytes(scene, hits, steps, dtype):
+    """Bytes the method itself reads and writes per frame (shading kernel and
+    pyramid build separately): per pixel the G-buffer record (depth 4 B plus
+    three 4-channel buffers minus the unused radiance channel: 48 B FP32,
+    26 B FP16/BF16) and the 12 B RGB output; per sample one 4 B depth or
+    pyramid texel per march iteration and one radiance read (12 B FP32 or
+    6 B FP16 at a hit pixel, 12 B for the environment otherwise); the pyramid
+    build reads the depth once and writes about a third of it."""
+    P = scene.width * scene.height
+    bg = 48 if dtype == "f32" else 26
+    br_hit = 12 if dtype == "f32" else 6
+    n_iter = int(steps.sum(dtype=np.int64))
+    valid = hits != -2
+    valid &= hits != -3
+    valid &= hits != -5
+    n_hit = int((hits >= 0).sum())
+    n_env = int(valid.sum()) - n_hit
+    shade = P * (bg + 12) + 4 * n_iter + br_hit * n_hit + 12 * n_env
+    hiz = P * 4 + 4 * int(sum(math.ceil(scene.width / 2 ** k) * math.ceil(scene.height / 2 ** k)
+                              for k in range(1, 13)))
+    return shade, hiz, dict(mean_iters=n_iter / max(1, int(valid.sum())), hit_frac=n_hit / hits.size)
+
+
+def time_gpu(ctx, scene, dtype, steps, warmup, dev, mips):
+    import torch
+
+    from paper_2504_01358_amd import ssr
+    t = upload(scene, dtype, dev)
+    H, W, S = scene.height, scene.width, scene.params["spp"]
+    out = torch.empty((H, W, 3), dtype=torch.float32, device=dev)
+    hiz = torch.empty(ssr.hiz_floats(W, H), dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    cam = ssr.make_camera(scene.camera)
+    prm = ssr.make_params(scene.params)
+
+    def step(ev=None):
+        if ev is not None:
+            ev[0].record(stream)
+        ssr.hiz_build(t["depth"], out=hiz, stream=stream)
+        if ev is not None:
+            ev[1].record(stream)
+        ctx.shade(cam, t["depth"], t["normal_rough"], t["albedo_metal"], t["radiance"], t["env"],
+                  prm, env_mips=mips, hiz=hiz, out=out, stream=stream)
+        if ev is not None:
+            ev[2].record(stream)
+
+    # untimed: the per-sample iteration counts and hit codes for the byte model
+    hits = torch.empty((H, W, S), dtype=torch.int32, device=dev)
+    nst = torch.empty((H, W, S), dtype=torch.int32, device=dev)
+    ctx.shade(cam, t["depth"], t["normal_rough"], t["albedo_metal"], t["radiance"], t["env"], prm,
+              env_mips=mips, out=out, hits=hits, steps=nst, stream=stream)
+    torch.cuda.synchronize()
+    hits_np, steps_np = hits.cpu().numpy(), nst.cpu().numpy()
+    del hits, nst
+
+    for _ in range(warmup):
+        step()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record(stream)
+    for k in range(steps):
+        step(evs[k])
+    end.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    total_ms = start.elapsed_time(end)
+    hiz_ms = [e[0].elapsed_time(e[1]) for e in evs]
+    shade_ms = [e[1].elapsed_time(e[2]) for e in evs]
+    b_shade, b_hiz, extra = algorithmic_bytes(scene, hits_np, steps_np, dtype)
+    return dict(ms_per_step=total_ms / steps, wall_ms_per_step=1e3 * wall / steps,
+                shade_ms=float(np.mean(shade_ms)), shade_ms_p50=float(np.median(shade_ms)),
+                shade_ms_p99=float(np.quantile(shade_ms, 0.99)), hiz_ms=float(np.mean(hiz_ms)),
+                bytes_shade=b_shade, bytes_hiz=b_hiz, **extra)
+
+
+def _oracle_rows(args):
+    cfg, rows = args
+    os.environ["OMP_NUM_THREADS"] = "1"
+    import oracle
+    import scenes
+    sc = scenes.make_scene(cfg)
+    g = dict(depth=sc.depth, normal_rough=sc.normal_rough, albedo_metal=sc.albedo_metal,
+             radiance=sc.radiance)
+    mips = oracle.env.build_mips(sc.env)
+    pyr = oracle.march.hiz_pyramid(sc.depth) if sc.params["march"] == 1 else None
+    t0 = time.perf_counter()
+    n = 0
+    for r in rows:
+        pix = np.arange(r * sc.width, (r + 1) * sc.width)
+        oracle.shade_pixels(sc.camera, g, sc.env, sc.params, pix, pyramid=pyr, mips=mips)
+        n += pix.size
+    return n, time.perf_counter() - t0
+
+
+def cpu_baseline(cfg, scene, row_stride):
+    """The FP64 oracle on every row_stride-th row of the frame, one worker
+    process per available core (row-interleaved), wall-clock timed."""
+    import multiprocessing as mp
+    cores = min(len(os.sched_getaffinity(0)), 16)
+    rows = list(range(0, scene.height, row_stride))
+    chunks = [rows[k::cores] for k in range(cores)]
+    chunks = [c for c in chunks if c]
+    ctx = mp.get_context("spawn")
+    t0 = time.perf_counter()
+    with ctx.Pool(len(chunks)) as pool:
+        res = pool.map(_oracle_rows, [(cfg, c) for c in chunks])
+    wall = time.perf_counter() - t0
+    busy = max(r[1] for r in res)
+    pixels = sum(r[0] for r in res)
+    rays = pixels * scene.params["spp"]
+    return dict(value=rays / busy / 1e6, unit="Mrays/s", cores=len(chunks), kind="oracle",
+                sample=f"every {row_stride}th row of the frame ({len(rows)} rows, {pixels} pixels, "
+                       f"{rays} rays), FP64 NumPy, {len(chunks)} worker processes; "
+                       f"{busy:.1f} s compute, {wall:.1f} s wall incl. start-up")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this path runs on one GPU; the multi-GPU layout is a design note only "
+              "(--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
+    import scenes
+    scene = scenes.make_scene(args.config)
+    # the CPU leg runs first, before anything initialises the GPU, so its
+    # worker processes start from a process with no device state
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(args.config, scene, args.cpu_rows or 8)
+        print(f"bench: oracle {cpu['value']:.3f} Mrays/s on {cpu['cores']} cores",
+              file=sys.stderr, flush=True)
+
+    import torch
+
+    from paper_2504_01358_amd import ssr
+    dev = torch.device("cuda", 0)
+    ctx = ssr.Context(0)
+    mips = ssr.env_build_mips(torch.from_numpy(scene.env).to(dev))
+    print(f"bench: {args.config} {scene.width}x{scene.height} spp={scene.params['spp']}",
+          file=sys.stderr, flush=True)
+    res = {"f32": time_gpu(ctx, scene, "f32", args.steps, args.warmup, dev, mips)}
+    print(f"bench: f32 {res['f32']['ms_per_step']:.3f} ms/frame", file=sys.stderr, flush=True)
+    if not args.no_variants:
+        for dt in ("f16", "bf16"):
+            res[dt] = time_gpu(ctx, scene, dt, args.steps, args.warmup, dev, mips)
+            print(f"bench: {dt} {res[dt]['ms_per_step']:.3f} ms/frame", file=sys.stderr, flush=True)
+    rays = scene.width * scene.height * scene.params["spp"]
+    r32 = res["f32"]
+    achieved = r32["bytes_shade"] / (r32["shade_ms"] * 1e-3) / 1e9
+    line = {
+        "metric": "Mrays/s + ms/frame at 1080p 16spp (FP32 vs FP16 G-buf); p50/p99 serve latency",
+        "value": rays / (r32["ms_per_step"] * 1e-3) / 1e6,
+        "unit": "Mrays/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r32["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.config}: {scene.width}x{scene.height}, "
+                               f"{scene.params['spp']} spp, hierarchical-Z march (<= "
+                               f"{scene.params['max_steps']} iterations, thickness 0.05), FP32 "
+                               "G-buffer; plane + 40 spheres + 60 boxes; env 512x256 lognormal(0,2)",
+                   "width": scene.width, "height": scene.height, "spp": scene.params["spp"],
+                   "march": "hiz", "max_steps": scene.params["max_steps"]},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "shade_kernel<f32,hiz>",
+                     "kernel_ms": r32["shade_ms"], "algorithmic_bytes": r32["bytes_shade"],
+                     "mean_iterations_per_sample": r32["mean_iters"]},
+        "hiz_build_ms": r32["hiz_ms"],
+    }
+    for dt in ("f16", "bf16"):
+        if dt in res:
+            line[dt] = {"value": rays / (res[dt]["ms_per_step"] * 1e-3) / 1e6,
+                        "ms_per_step": res[dt]["ms_per_step"], "shade_ms": res[dt]["shade_ms"]}
+    if cpu is not None:
+        line["cpu_baseline"] = cpu
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,186 @@
+/*
+ * ssr.h - screen-space GGX shading of a G-buffer on AMD Instinct MI355X (gfx950).
+ *
+ * The operation (3D Gaussian Inverse Rendering with Approximated Global
+ * Illumination, Sec. 3.2 and Sec. 3.3): for every pixel of a deferred
+ * G-buffer (Eq. g-buffer: depth, normal, albedo, roughness, metallic, plus the
+ * first-pass radiance c1 of Sec. 3.2), output
+ *
+ *     c = c_d + c_s'
+ *
+ * where c_d = (1 - m) a E_lambda(n) is the direct diffuse light read from an
+ * HDR environment map at the roughness mip level lambda = log2(1 + rho)
+ * lambda_max (Sec. 3.2, "Shading"), and c_s' is the Monte-Carlo estimate of
+ * the specular integral (Sec. 3.3, the estimator over N_s sampled rays): each
+ * sample draws a GGX visible normal, reflects the view direction about it,
+ * marches the ray in screen space against the depth buffer (Sec. 3.3 and
+ * Appendix D, Algorithm 1, or a hierarchical-Z version of the same test), and
+ * weights the radiance found at the hit (c1 of the hit pixel; the environment
+ * when the ray leaves the screen) by F(wo.h) G1(n.l) (Appendix B with
+ * alpha = rho).
+ *
+ * Conventions.  World space is right-handed, +y up.  View coordinates of a
+ * world point x: X = (x-pos).right, Y = (x-pos).up, Z = (x-pos).forward; Z is
+ * the linear depth.  Pixel (i, j) covers [i, i+1) x [j, j+1), row 0 on top,
+ * projects as px = cx + fx X/Z, py = cy - fy Y/Z and is un-projected at its
+ * centre.  The environment is equirectangular: direction d maps to
+ * u = 1/2 + atan2(d.x, -d.z)/(2 pi), v = acos(d.y)/pi.
+ *
+ * Memory.  Every buffer pointer below is a DEVICE pointer on the context's
+ * device, owned by the caller; the library never frees caller memory.  Work
+ * is enqueued on `stream` (a hipStream_t passed as void*; NULL = the null
+ * stream) and returns before it finishes: the caller synchronises.
+ *
+ * Errors.  Every call returns an ssr_status.  Arguments are checked before
+ * anything is enqueued; a rejected call enqueues nothing.  A failure reported
+ * by the HIP runtime is returned as SSR_E_HIP (an earlier asynchronous fault
+ * may surface there).  Nothing is thrown across this interface.
+ *
+ * Threads.  An ssr_ctx is used by one host thread at a time, and calls made
+ * with the same context on different streams must be ordered by the caller
+ * (they share the context's workspace).
+ */
+#ifndef SSR_H
+#define SSR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ssr_ctx ssr_ctx;
+
+typedef enum {
+    SSR_OK = 0,
+    SSR_E_ARG = -1,    /* a pointer, size, mode or parameter is invalid          */
+    SSR_E_DTYPE = -2,  /* unknown G-buffer storage type                          */
+    SSR_E_NOMEM = -3,  /* the context's workspace could not be allocated         */
+    SSR_E_HIP = -4,    /* the HIP runtime reported an error                      */
+    SSR_E_DEVICE = -5  /* no such device, or it is not a gfx950 device          */
+} ssr_status;
+
+/* Storage type of the three packed G-buffers (depth is always float32). */
+typedef enum { SSR_F32 = 0, SSR_F16 = 1, SSR_BF16 = 2 } ssr_dtype;
+
+/* March modes.  LINEAR: fixed world-space steps (Appendix D, Algorithm 1).
+ * HIZ: exact first hit on the depth heightfield, traversed over a min-depth
+ * pyramid with at most max_steps iterations. */
+enum { SSR_MARCH_LINEAR = 0, SSR_MARCH_HIZ = 1 };
+
+/* Flags: drop the direct diffuse term, or the Monte-Carlo specular term. */
+enum { SSR_NO_DIRECT = 1u, SSR_NO_SPECULAR = 2u };
+
+/* Per-sample hit codes written to out_hits (>= 0: hit pixel index j*W + i). */
+enum {
+    SSR_HIT_OFFSCREEN = -1,  /* left the screen or the ray segment: env read    */
+    SSR_HIT_INVALID = -2,    /* sampled direction below the surface, or the
+                                pixel faces away from the camera: weight 0     */
+    SSR_HIT_BACKGROUND = -3, /* background pixel (depth not finite)            */
+    SSR_HIT_CAP = -4,        /* iteration cap reached: env read                */
+    SSR_HIT_SKIPPED = -5     /* SSR_NO_SPECULAR set                            */
+};
+
+typedef struct {
+    int32_t width, height; /* pixels; 0 <= width, height <= 16384              */
+    float pos[3];          /* camera position (world)                           */
+    float rot[9];          /* rows: right, up, forward (world, orthonormal)     */
+    float fx, fy, cx, cy;  /* pinhole intrinsics in pixels                      */
+    float z_near;          /* rays are clipped where view depth reaches z_near  */
+} ssr_camera;
+
+typedef struct {
+    const float* depth;       /* [H][W] float32 view-space linear depth; +inf (or
+                                 any non-finite value) marks background; no NaN  */
+    const void* normal_rough; /* [H][W][4] (n.x, n.y, n.z, roughness), world n,
+                                 need not be unit length but must be non-zero   */
+    const void* albedo_metal; /* [H][W][4] (a.r, a.g, a.b, metallic)             */
+    const void* radiance;     /* [H][W][4] (c1.r, c1.g, c1.b, unused): the
+                                 first-pass radiance read at hit pixels         */
+    int32_t dtype;            /* ssr_dtype of the three [H][W][4] buffers        */
+    const float* hiz;         /* NULL, or levels 1..top of this depth buffer's
+                                 min pyramid as ssr_hiz_build wrote them (then
+                                 ssr_shade does not build it)                   */
+} ssr_gbuffer;
+
+typedef struct {
+    const float* rgb;  /* [He][We][3] float32 equirect map, texel (x, y) centred at
+                          u = (x+1/2)/We, v = (y+1/2)/He                          */
+    int32_t width;     /* We = 2 * He                                             */
+    int32_t height;    /* He, a power of two, 1 <= He <= 8192                     */
+    const float* mips; /* NULL, or the buffer ssr_env_build_mips filled from this
+                          exact map (then no mip chain is built per call)        */
+} ssr_env;
+
+typedef struct {
+    int32_t spp;       /* samples per pixel N_s, 1..4096 (Sec. 3.3 uses 8)        */
+    int32_t march;     /* SSR_MARCH_LINEAR or SSR_MARCH_HIZ                       */
+    int32_t max_steps; /* linear: samples; hiz: iterations; 1..2^20               */
+    float step_len;    /* linear: world-space step (> 0); unused by hiz          */
+    float max_dist;    /* world-space ray length (> 0)                            */
+    float thickness;   /* depth slab behind a surface that counts as a hit (>= 0) */
+    uint64_t seed;     /* Philox key: (seed mod 2^32, seed >> 32)                 */
+    uint32_t frame;    /* third Philox counter word                               */
+    uint32_t flags;    /* SSR_NO_DIRECT | SSR_NO_SPECULAR                         */
+} ssr_params;
+
+/* Create a context on HIP device `device` (must be gfx950).  The context owns
+ * a grow-only workspace (min-depth pyramid, env mip chain).  *out is set to
+ * NULL on failure. */
+int ssr_ctx_create(int device, ssr_ctx** out);
+
+/* Free the context and its workspace after waiting for the device.  NULL is
+ * accepted. */
+void ssr_ctx_destroy(ssr_ctx* ctx);
+
+/* Shade one frame (Sec. 3.2 diffuse + Sec. 3.3 Monte-Carlo specular).
+ *   out_rgb   [H][W][3] float32, written: linear HDR c_d + c_s' (no tone map).
+ *   out_hits  NULL or [H][W][spp] int32: per-sample hit pixel or SSR_HIT_* code.
+ *   out_steps NULL or [H][W][spp] int32: march iterations each sample used.
+ * Sample s of pixel q = j*W + i draws Philox4x32-10 with counter
+ * (q, s, frame, 0): u1 = (x0 >> 8) 2^-24 picks the azimuth, u2 = (x1 >> 8) 2^-24
+ * the cap height of the visible-normal sample.  width or height 0 is a no-op.
+ * In hiz mode the min-depth pyramid is built in the context's workspace unless
+ * gbuf->hiz supplies it; the env mip chain likewise unless env->mips does.
+ * Both builds run on `stream` before the shading kernel. */
+int ssr_shade(ssr_ctx* ctx, const ssr_camera* cam, const ssr_gbuffer* gbuf,
+              const ssr_env* env, const ssr_params* params, float* out_rgb,
+              int32_t* out_hits, int32_t* out_steps, void* stream);
+
+/* Number of floats of the env mip-chain buffer for a We x He map (0 if the
+ * dimensions are invalid). */
+int64_t ssr_env_mips_floats(int32_t width, int32_t height);
+
+/* Fill `mips` (ssr_env_mips_floats floats) with levels 0..log2(He) of the map:
+ * level k is the 2x2 box mean of level k-1 (Sec. 3.2, SampleEnvMap mip levels),
+ * stored as RGBA float32 texels, level after level.  The layout is private to
+ * the library; pass the buffer back through ssr_env.mips. */
+int ssr_env_build_mips(const float* rgb, int32_t width, int32_t height, float* mips,
+                       void* stream);
+
+/* Number of floats of levels 1..top of the min-depth pyramid of a W x H depth
+ * buffer (0 for an empty or oversized image). */
+int64_t ssr_hiz_floats(int32_t width, int32_t height);
+
+/* Fill `pyramid` with levels 1..top of the min-depth pyramid: level L has
+ * ceil(W_{L-1}/2) x ceil(H_{L-1}/2) texels, each the minimum of its existing
+ * children, row-major, level after level, ending at 1 x 1.  Level 0 is the
+ * depth buffer itself and is not copied.  Pass the buffer to ssr_shade
+ * through ssr_gbuffer.hiz to reuse it. */
+int ssr_hiz_build(const float* depth, int32_t width, int32_t height, float* pyramid,
+                  void* stream);
+
+/* Philox4x32-10 (Salmon et al., SC'11) of n counters: ctr [n][4], key [n][2],
+ * out [n][4], all uint32 device buffers.  The same generator ssr_shade draws
+ * its samples from. */
+int ssr_philox4x32_10(const uint32_t* ctr, const uint32_t* key, int64_t n, uint32_t* out,
+                      void* stream);
+
+/* Static description of a status code. */
+const char* ssr_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SSR_H */

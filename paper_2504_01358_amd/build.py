@@ -1,0 +1,43 @@
+"""Build the HIP library ``libssr.so`` in-tree for gfx950.
+
+``python -m paper_2504_01358_amd.build`` (or ``build()``) compiles every
+source under ``csrc/`` with hipcc into ``paper_2504_01358_amd/libssr.so``.
+Packed-FP32 instructions are disabled on the device side.
+"""
+
+import os
+import subprocess
+import sys
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+CSRC = os.path.join(PKG, "csrc")
+LIB = os.path.join(PKG, "libssr.so")
+SOURCES = ["abi.hip", "pyramids.hip", "shade.hip"]
+
+
+def command(out=LIB, extra=()):
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    return [hipcc, "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            "-Wall", "-Wno-unused-result",
+            "-I", os.path.join(ROOT, "include"), "-I", CSRC,
+            *extra,
+            *[os.path.join(CSRC, s) for s in SOURCES], "-o", out]
+
+
+def build(verbose=False):
+    tmp = LIB + ".tmp"
+    cmd = command(tmp)
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        sys.stderr.write(res.stdout + res.stderr)
+        raise RuntimeError("hipcc failed building libssr.so")
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose=True))

@@ -1,0 +1,239 @@
+// C-ABI entry points (declared in include/ssr.h): argument validation, the
+// context's grow-only device workspace, and the launches.
+#include <math.h>
+#include <string.h>
+
+#include <new>
+
+#include "kernels.h"
+#include "ssr.h"
+
+struct ssr_ctx {
+    int device;
+    // workspace: min-depth pyramid (levels 1..top) and env mip chain
+    float* hiz;
+    int64_t hiz_cap;    // floats
+    float4* mips;
+    int64_t mips_cap;   // float4 texels
+};
+
+namespace {
+
+int hip_status(hipError_t e) { return e == hipSuccess ? SSR_OK : SSR_E_HIP; }
+
+// Grow a workspace buffer.  The old buffer may still be read by work queued
+// earlier, so the device is drained before it is freed (growth is rare: the
+// buffers only ever get larger).
+template <typename T>
+int ensure(T** buf, int64_t* cap, int64_t need) {
+    if (need <= *cap) return SSR_OK;
+    if (*buf) {
+        if (hipDeviceSynchronize() != hipSuccess) return SSR_E_HIP;
+        if (hipFree(*buf) != hipSuccess) return SSR_E_HIP;
+        *buf = nullptr;
+        *cap = 0;
+    }
+    void* p = nullptr;
+    if (hipMalloc(&p, static_cast<size_t>(need) * sizeof(T)) != hipSuccess) {
+        (void)hipGetLastError();
+        return SSR_E_NOMEM;
+    }
+    *buf = static_cast<T*>(p);
+    *cap = need;
+    return SSR_OK;
+}
+
+bool finite_f(float v) { return isfinite(v) != 0; }
+
+int check_camera(const ssr_camera* c) {
+    if (!c) return SSR_E_ARG;
+    if (c->width < 0 || c->height < 0 || c->width > 16384 || c->height > 16384) return SSR_E_ARG;
+    for (int k = 0; k < 3; ++k)
+        if (!finite_f(c->pos[k])) return SSR_E_ARG;
+    for (int k = 0; k < 9; ++k)
+        if (!finite_f(c->rot[k])) return SSR_E_ARG;
+    if (!(c->fx > 0.0f) || !(c->fy > 0.0f) || !finite_f(c->fx) || !finite_f(c->fy) ||
+        !finite_f(c->cx) || !finite_f(c->cy) || !(c->z_near > 0.0f) || !finite_f(c->z_near))
+        return SSR_E_ARG;
+    return SSR_OK;
+}
+
+int check_params(const ssr_params* p) {
+    if (!p) return SSR_E_ARG;
+    if (p->spp < 1 || p->spp > 4096) return SSR_E_ARG;
+    if (p->march != SSR_MARCH_LINEAR && p->march != SSR_MARCH_HIZ) return SSR_E_ARG;
+    if (p->max_steps < 1 || p->max_steps > (1 << 20)) return SSR_E_ARG;
+    if (!(p->max_dist > 0.0f) || !finite_f(p->max_dist)) return SSR_E_ARG;
+    if (!(p->thickness >= 0.0f) || !finite_f(p->thickness)) return SSR_E_ARG;
+    if (p->march == SSR_MARCH_LINEAR && (!(p->step_len > 0.0f) || !finite_f(p->step_len)))
+        return SSR_E_ARG;
+    if (p->flags & ~static_cast<uint32_t>(SSR_NO_DIRECT | SSR_NO_SPECULAR)) return SSR_E_ARG;
+    return SSR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ssr_status_string(int status) {
+    switch (status) {
+        case SSR_OK: return "ok";
+        case SSR_E_ARG: return "invalid argument";
+        case SSR_E_DTYPE: return "unknown G-buffer storage type";
+        case SSR_E_NOMEM: return "device workspace allocation failed";
+        case SSR_E_HIP: return "HIP runtime error";
+        case SSR_E_DEVICE: return "no such device or not a gfx950 device";
+        default: return "unknown status";
+    }
+}
+
+int ssr_ctx_create(int device, ssr_ctx** out) {
+    if (!out) return SSR_E_ARG;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) {
+        (void)hipGetLastError();
+        return SSR_E_DEVICE;
+    }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return SSR_E_HIP;
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) return SSR_E_DEVICE;
+    ssr_ctx* c = new (std::nothrow) ssr_ctx;
+    if (!c) return SSR_E_NOMEM;
+    c->device = device;
+    c->hiz = nullptr;
+    c->hiz_cap = 0;
+    c->mips = nullptr;
+    c->mips_cap = 0;
+    *out = c;
+    return SSR_OK;
+}
+
+void ssr_ctx_destroy(ssr_ctx* ctx) {
+    if (!ctx) return;
+    if (hipSetDevice(ctx->device) == hipSuccess) {
+        (void)hipDeviceSynchronize();
+        if (ctx->hiz) (void)hipFree(ctx->hiz);
+        if (ctx->mips) (void)hipFree(ctx->mips);
+    }
+    delete ctx;
+}
+
+int64_t ssr_env_mips_floats(int32_t width, int32_t height) {
+    ssr::EnvLayout lay;
+    if (!ssr::make_env_layout(width, height, &lay)) return 0;
+    return 4 * lay.total;
+}
+
+int ssr_env_build_mips(const float* rgb, int32_t width, int32_t height, float* mips,
+                       void* stream) {
+    ssr::EnvLayout lay;
+    if (!rgb || !mips || !ssr::make_env_layout(width, height, &lay)) return SSR_E_ARG;
+    return hip_status(ssr::launch_env_mips(rgb, lay, reinterpret_cast<float4*>(mips),
+                                           static_cast<hipStream_t>(stream)));
+}
+
+int64_t ssr_hiz_floats(int32_t width, int32_t height) {
+    ssr::HizLayout lay;
+    if (!ssr::make_hiz_layout(width, height, &lay)) return 0;
+    return lay.total;
+}
+
+int ssr_hiz_build(const float* depth, int32_t width, int32_t height, float* pyramid,
+                  void* stream) {
+    ssr::HizLayout lay;
+    if (!depth || !ssr::make_hiz_layout(width, height, &lay)) return SSR_E_ARG;
+    if (lay.total > 0 && !pyramid) return SSR_E_ARG;
+    return hip_status(ssr::launch_hiz(depth, lay, pyramid, static_cast<hipStream_t>(stream)));
+}
+
+int ssr_philox4x32_10(const uint32_t* ctr, const uint32_t* key, int64_t n, uint32_t* out,
+                      void* stream) {
+    if (n < 0 || n > (int64_t(1) << 31) * 255) return SSR_E_ARG;
+    if (n == 0) return SSR_OK;
+    if (!ctr || !key || !out) return SSR_E_ARG;
+    return hip_status(ssr::launch_philox(ctr, key, n, out, static_cast<hipStream_t>(stream)));
+}
+
+int ssr_shade(ssr_ctx* ctx, const ssr_camera* cam, const ssr_gbuffer* g, const ssr_env* env,
+              const ssr_params* p, float* out_rgb, int32_t* out_hits, int32_t* out_steps,
+              void* stream) {
+    if (!ctx || !g || !env) return SSR_E_ARG;
+    int st = check_camera(cam);
+    if (st != SSR_OK) return st;
+    st = check_params(p);
+    if (st != SSR_OK) return st;
+    if (g->dtype != SSR_F32 && g->dtype != SSR_F16 && g->dtype != SSR_BF16) return SSR_E_DTYPE;
+    ssr::EnvLayout env_lay;
+    if (!env->rgb || !ssr::make_env_layout(env->width, env->height, &env_lay)) return SSR_E_ARG;
+    if (cam->width == 0 || cam->height == 0) return SSR_OK;
+    if (!g->depth || !g->normal_rough || !g->albedo_metal || !g->radiance || !out_rgb)
+        return SSR_E_ARG;
+    ssr::HizLayout hiz_lay;
+    if (!ssr::make_hiz_layout(cam->width, cam->height, &hiz_lay)) return SSR_E_ARG;
+
+    if (hipSetDevice(ctx->device) != hipSuccess) return SSR_E_HIP;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+
+    const float4* mips = reinterpret_cast<const float4*>(env->mips);
+    if (!mips) {
+        st = ensure(&ctx->mips, &ctx->mips_cap, env_lay.total);
+        if (st != SSR_OK) return st;
+        st = hip_status(ssr::launch_env_mips(env->rgb, env_lay, ctx->mips, s));
+        if (st != SSR_OK) return st;
+        mips = ctx->mips;
+    }
+    const float* hiz = g->hiz;
+    if (p->march == SSR_MARCH_HIZ && hiz_lay.total > 0 && !hiz) {
+        st = ensure(&ctx->hiz, &ctx->hiz_cap, hiz_lay.total);
+        if (st != SSR_OK) return st;
+        st = hip_status(ssr::launch_hiz(g->depth, hiz_lay, ctx->hiz, s));
+        if (st != SSR_OK) return st;
+        hiz = ctx->hiz;
+    }
+
+    ssr::ShadeArgs a;
+    memset(&a, 0, sizeof(a));
+    a.W = cam->width;
+    a.H = cam->height;
+    for (int k = 0; k < 3; ++k) {
+        a.pos[k] = cam->pos[k];
+        a.right[k] = cam->rot[k];
+        a.up[k] = cam->rot[3 + k];
+        a.fwd[k] = cam->rot[6 + k];
+    }
+    a.fx = cam->fx;
+    a.fy = cam->fy;
+    a.cx = cam->cx;
+    a.cy = cam->cy;
+    a.z_near = cam->z_near;
+    a.depth = g->depth;
+    a.normal_rough = g->normal_rough;
+    a.albedo_metal = g->albedo_metal;
+    a.radiance = g->radiance;
+    a.env = mips;
+    a.env_lay = env_lay;
+    a.hiz = hiz;
+    a.hiz_lay = hiz_lay;
+    a.spp = p->spp;
+    a.max_steps = p->max_steps;
+    // linear march: samples t_k = k * step_len for k = 1..K, K = min(max_steps,
+    // floor(max_dist / step_len)), evaluated in double as the specification states
+    {
+        const double k = floor(static_cast<double>(p->max_dist) / static_cast<double>(p->step_len));
+        a.linear_samples = k < static_cast<double>(p->max_steps) ? static_cast<int>(k) : p->max_steps;
+    }
+    a.step_len = p->step_len;
+    a.max_dist = p->max_dist;
+    a.thickness = p->thickness;
+    a.key0 = static_cast<uint32_t>(p->seed & 0xFFFFFFFFu);
+    a.key1 = static_cast<uint32_t>(p->seed >> 32);
+    a.frame = p->frame;
+    a.flags = p->flags;
+    a.out = out_rgb;
+    a.hits = out_hits;
+    a.steps = out_steps;
+    return hip_status(ssr::launch_shade(a, g->dtype, p->march, s));
+}
+
+}  // extern "C"

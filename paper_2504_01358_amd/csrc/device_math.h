@@ -1,0 +1,169 @@
+// Device helpers shared by the shading kernels: counter-based random numbers,
+// equirect environment filtering and the GGX microfacet pieces.  Everything
+// is float32 (no float64 on the device); where a plain formula would lose
+// accuracy that the environment map's contrast turns into visible error, the
+// evaluation is rearranged (comments say how) so that it stays exact to a few
+// float32 ulps of the sampled direction.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ssr {
+
+// ----------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two 32x32
+// multiplies whose high halves are mixed with the other counter words and the
+// round key; the key advances by two Weyl constants between rounds.
+// ----------------------------------------------------------------------------
+struct Philox {
+    static constexpr uint32_t kMul0 = 0xD2511F53u;
+    static constexpr uint32_t kMul1 = 0xCD9E8D57u;
+    static constexpr uint32_t kWeyl0 = 0x9E3779B9u;
+    static constexpr uint32_t kWeyl1 = 0xBB67AE85u;
+};
+
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += Philox::kWeyl0;
+            k1 += Philox::kWeyl1;
+        }
+        const uint32_t lo0 = Philox::kMul0 * c.x;
+        const uint32_t hi0 = __umulhi(Philox::kMul0, c.x);
+        const uint32_t lo1 = Philox::kMul1 * c.z;
+        const uint32_t hi1 = __umulhi(Philox::kMul1, c.z);
+        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+    }
+    return c;
+}
+
+// 24 random bits -> [0, 1), a multiple of 2^-24 (exact in float32).
+__device__ __forceinline__ float unit24(uint32_t x) {
+    return static_cast<float>(x >> 8) * (1.0f / 16777216.0f);
+}
+
+// ----------------------------------------------------------------------------
+// Small vector helpers.
+// ----------------------------------------------------------------------------
+struct V3 {
+    float x, y, z;
+};
+
+__device__ __forceinline__ V3 v3(float x, float y, float z) { return V3{x, y, z}; }
+__device__ __forceinline__ V3 operator+(V3 a, V3 b) { return v3(a.x + b.x, a.y + b.y, a.z + b.z); }
+__device__ __forceinline__ V3 operator-(V3 a, V3 b) { return v3(a.x - b.x, a.y - b.y, a.z - b.z); }
+__device__ __forceinline__ V3 operator*(float s, V3 a) { return v3(s * a.x, s * a.y, s * a.z); }
+__device__ __forceinline__ float dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ V3 normalize(V3 a) {
+    const float inv = 1.0f / sqrtf(dot(a, a));
+    return inv * a;
+}
+
+// ----------------------------------------------------------------------------
+// Equirect lookup.  Direction d -> azimuth phi = atan2(d.x, -d.z) in (-pi, pi]
+// and polar angle theta = atan2(|d.xz|, d.y) in [0, pi] (the atan2 form keeps
+// full accuracy near the poles, where acos(d.y) does not).  Texel coordinate
+// x = (W/2 - 1/2) + phi * W/(2 pi), y = theta * H/pi - 1/2.
+//
+// The products are carried as float-float values: the scale constants come
+// in (hi, lo) pairs, the product error is recovered with an FMA and the sum
+// with the offset by an exact two-sum, so the fractional texel position is
+// accurate to ~1e-7 of a texel instead of the ~1.5e-5 that rounding x itself
+// to float32 at magnitude 256 would give.
+// ----------------------------------------------------------------------------
+struct EnvLevel {
+    const float4* texels;  // [h][w] RGBA
+    int w, h;
+};
+
+struct TexelCoord {
+    int i0;     // integer part (may be -1 or the size at the edges)
+    float f;    // fractional part in [0, 1)
+};
+
+__device__ __forceinline__ TexelCoord texel_coord(float ang, float scale_hi, float scale_lo,
+                                                  float offset) {
+#pragma clang fp contract(off)
+    const float t = ang * scale_hi;
+    const float te = fmaf(ang, scale_hi, -t) + ang * scale_lo;
+    const float x = offset + t;
+    const float bp = x - offset;
+    const float e = (offset - (x - bp)) + (t - bp);
+    float fl = floorf(x);
+    float fr = (x - fl) + (e + te);
+    if (fr < 0.0f) {
+        fr += 1.0f;
+        fl -= 1.0f;
+    } else if (fr >= 1.0f) {
+        fr -= 1.0f;
+        fl += 1.0f;
+    }
+    return TexelCoord{static_cast<int>(fl), fr};
+}
+
+struct EnvAngles {
+    float phi, theta;
+};
+
+__device__ __forceinline__ EnvAngles env_angles(V3 d) {
+    return EnvAngles{atan2f(d.x, -d.z), atan2f(sqrtf(d.x * d.x + d.z * d.z), d.y)};
+}
+
+// 1/(2 pi) and 1/pi as float-float pairs (hi + lo to ~1e-15).
+constexpr float kInv2PiHi = 0x1.45f306p-3f;   // 0.15915494
+constexpr float kInv2PiLo = 0x1.b93910p-28f;  // 6.4206382e-09
+constexpr float kInvPiHi = 0x1.45f306p-2f;    // 0.31830987
+constexpr float kInvPiLo = 0x1.b93910p-27f;   // 1.2841276e-08
+
+__device__ __forceinline__ float3 env_bilinear(const EnvLevel& lv, EnvAngles a) {
+    const float wf = static_cast<float>(lv.w);
+    const float hf = static_cast<float>(lv.h);
+    const TexelCoord cx = texel_coord(a.phi, kInv2PiHi * wf, kInv2PiLo * wf, 0.5f * wf - 0.5f);
+    const TexelCoord cy = texel_coord(a.theta, kInvPiHi * hf, kInvPiLo * hf, -0.5f);
+    int x0 = cx.i0 % lv.w;
+    if (x0 < 0) x0 += lv.w;
+    int x1 = x0 + 1;
+    if (x1 == lv.w) x1 = 0;
+    const int y0 = min(max(cy.i0, 0), lv.h - 1);
+    const int y1 = min(max(cy.i0 + 1, 0), lv.h - 1);
+    const float4 t00 = lv.texels[y0 * lv.w + x0];
+    const float4 t01 = lv.texels[y0 * lv.w + x1];
+    const float4 t10 = lv.texels[y1 * lv.w + x0];
+    const float4 t11 = lv.texels[y1 * lv.w + x1];
+    const float fx = cx.f, fy = cy.f;
+    const float w00 = (1.0f - fx) * (1.0f - fy), w01 = fx * (1.0f - fy);
+    const float w10 = (1.0f - fx) * fy, w11 = fx * fy;
+    return make_float3(w00 * t00.x + w01 * t01.x + w10 * t10.x + w11 * t11.x,
+                       w00 * t00.y + w01 * t01.y + w10 * t10.y + w11 * t11.y,
+                       w00 * t00.z + w01 * t01.z + w10 * t10.z + w11 * t11.z);
+}
+
+// Compensated (Kahan) accumulation of one channel: sum + comp carries the
+// running total to about one float32 ulp regardless of the sample count.
+__device__ __forceinline__ void kahan_add(float& sum, float& comp, float v) {
+#pragma clang fp contract(off)
+    const float y = v - comp;
+    const float t = sum + y;
+    comp = (t - sum) - y;
+    sum = t;
+}
+
+// ----------------------------------------------------------------------------
+// GGX with alpha = rho (Appendix B as written).
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ float smith_g1(float z, float a2) {
+    return 2.0f * z / (z + sqrtf(a2 + (1.0f - a2) * z * z));
+}
+
+// Branchless tangent frame (Duff et al., JCGT 2017); sign(+0) = +1.
+__device__ __forceinline__ void onb(V3 n, V3& t, V3& b) {
+    const float sign = copysignf(1.0f, n.z);
+    const float a = -1.0f / (sign + n.z);
+    const float bb = n.x * n.y * a;
+    t = v3(1.0f + sign * n.x * n.x * a, sign * bb, -sign * n.x);
+    b = v3(bb, sign + n.y * n.y * a, -n.y);
+}
+
+}  // namespace ssr

@@ -1,0 +1,66 @@
+// Internal interface between the C-ABI layer and the HIP kernels: buffer
+// layouts and launchers.  Not part of the public header.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ssr.h"
+
+namespace ssr {
+
+constexpr int kMaxLevels = 16;
+
+// Env mip chain: levels 0..top of a W x H equirect map (W = 2H, H a power of
+// two), level k of size (W >> k) x (H >> k), stored as float4 RGBA texels,
+// level after level.
+struct EnvLayout {
+    int levels;               // top + 1
+    int w[kMaxLevels], h[kMaxLevels];
+    int64_t offset[kMaxLevels];  // in float4 texels
+    int64_t total;               // float4 texels
+};
+
+// Min-depth pyramid: level 0 is the caller's depth buffer; levels 1..top are
+// stored row-major, level after level, in one float buffer.
+struct HizLayout {
+    int levels;               // top + 1
+    int w[kMaxLevels + 1], h[kMaxLevels + 1];
+    int64_t offset[kMaxLevels + 1];  // in floats; offset[0] unused
+    int64_t total;                   // floats for levels 1..top
+};
+
+bool make_env_layout(int w, int h, EnvLayout* out);
+bool make_hiz_layout(int w, int h, HizLayout* out);
+
+// Everything the shading kernel reads, by value.
+struct ShadeArgs {
+    int W, H;
+    float pos[3];
+    float right[3], up[3], fwd[3];
+    float fx, fy, cx, cy, z_near;
+    const float* depth;
+    const void* normal_rough;
+    const void* albedo_metal;
+    const void* radiance;
+    const float4* env;        // mip chain (EnvLayout)
+    EnvLayout env_lay;
+    const float* hiz;         // levels 1..top (HizLayout)
+    HizLayout hiz_lay;
+    int spp, max_steps, linear_samples;
+    float step_len, max_dist, thickness;
+    uint32_t key0, key1, frame, flags;
+    float* out;
+    int32_t* hits;
+    int32_t* steps;
+};
+
+hipError_t launch_env_mips(const float* rgb, const EnvLayout& lay, float4* mips,
+                           hipStream_t stream);
+hipError_t launch_hiz(const float* depth, const HizLayout& lay, float* pyramid,
+                      hipStream_t stream);
+hipError_t launch_shade(const ShadeArgs& args, int dtype, int march, hipStream_t stream);
+hipError_t launch_philox(const uint32_t* ctr, const uint32_t* key, int64_t n, uint32_t* out,
+                         hipStream_t stream);
+
+}  // namespace ssr

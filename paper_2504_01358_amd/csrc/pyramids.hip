@@ -1,0 +1,251 @@
+// Builders for the two pyramids the shading kernel reads:
+//  * the environment mip chain (Sec. 3.2, SampleEnvMap at level lambda):
+//    level k is the 2x2 box mean of level k-1;
+//  * the min-depth pyramid used by the hierarchical march: level L is the
+//    minimum of the (up to four) level L-1 children, ceil-halving to 1 x 1.
+#include "device_math.h"
+#include "kernels.h"
+
+namespace ssr {
+
+bool make_env_layout(int w, int h, EnvLayout* out) {
+    if (h < 1 || h > 8192 || (h & (h - 1)) != 0 || w != 2 * h) return false;
+    int levels = 0;
+    int64_t off = 0;
+    for (int k = 0;; ++k) {
+        out->w[k] = w >> k;
+        out->h[k] = h >> k;
+        out->offset[k] = off;
+        off += static_cast<int64_t>(out->w[k]) * out->h[k];
+        levels = k + 1;
+        if (out->h[k] == 1) break;
+    }
+    out->levels = levels;
+    out->total = off;
+    return true;
+}
+
+bool make_hiz_layout(int w, int h, HizLayout* out) {
+    if (w < 1 || h < 1 || w > 16384 || h > 16384) return false;
+    int lw = w, lh = h, L = 0;
+    int64_t off = 0;
+    out->w[0] = w;
+    out->h[0] = h;
+    out->offset[0] = 0;
+    while (lw > 1 || lh > 1) {
+        lw = (lw + 1) / 2;
+        lh = (lh + 1) / 2;
+        ++L;
+        out->w[L] = lw;
+        out->h[L] = lh;
+        out->offset[L] = off;
+        off += static_cast<int64_t>(lw) * lh;
+    }
+    out->levels = L + 1;
+    out->total = off;
+    return true;
+}
+
+// ---------------------------------------------------------------- env mips --
+
+__global__ void env_level0_kernel(const float* __restrict__ rgb, float4* __restrict__ dst, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    dst[i] = make_float4(rgb[3 * i + 0], rgb[3 * i + 1], rgb[3 * i + 2], 0.0f);
+}
+
+__global__ void env_down_kernel(const float4* __restrict__ src, float4* __restrict__ dst, int sw,
+                                int dw, int dh) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= dw * dh) return;
+    const int x = i % dw, y = i / dw;
+    const float4 a = src[(2 * y) * sw + 2 * x], b = src[(2 * y) * sw + 2 * x + 1];
+    const float4 c = src[(2 * y + 1) * sw + 2 * x], d = src[(2 * y + 1) * sw + 2 * x + 1];
+    dst[i] = make_float4(((a.x + b.x) + (c.x + d.x)) * 0.25f, ((a.y + b.y) + (c.y + d.y)) * 0.25f,
+                         ((a.z + b.z) + (c.z + d.z)) * 0.25f, 0.0f);
+}
+
+hipError_t launch_env_mips(const float* rgb, const EnvLayout& lay, float4* mips,
+                           hipStream_t stream) {
+    const int n0 = lay.w[0] * lay.h[0];
+    hipLaunchKernelGGL(env_level0_kernel, dim3((n0 + 255) / 256), dim3(256), 0, stream, rgb, mips,
+                       n0);
+    for (int k = 1; k < lay.levels; ++k) {
+        const int n = lay.w[k] * lay.h[k];
+        hipLaunchKernelGGL(env_down_kernel, dim3((n + 255) / 256), dim3(256), 0, stream,
+                           mips + lay.offset[k - 1], mips + lay.offset[k], lay.w[k - 1], lay.w[k],
+                           lay.h[k]);
+    }
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ Hi-Z pyramid --
+//
+// Pass 1: one 256-thread workgroup per 64 x 64 depth tile produces levels
+// 1..6 of that tile.  Each thread reduces a 4 x 4 pixel block to its two
+// level-1 rows and one level-2 texel in registers; the 16 x 16 level-2 texels
+// go through LDS for levels 3..6.  A texel at level L is the minimum of the
+// 2^L x 2^L pixel block it covers, clipped to the image (pixels outside count
+// as +inf), which equals the ceil-halving recursion.  Texels that do not
+// exist at their level (index >= W_L or H_L) are not written.
+//
+// Pass 2: the levels above 6.  When level 6 fits in LDS, one workgroup does
+// them all there; otherwise one launch per level from global memory.
+
+constexpr int kTile = 64;
+constexpr int kTileLevels = 6;
+
+__device__ __forceinline__ float depth_at(const float* __restrict__ d, int W, int H, int x, int y) {
+    return (x < W && y < H) ? d[static_cast<int64_t>(y) * W + x] : INFINITY;
+}
+
+__global__ __launch_bounds__(256) void hiz_tile_kernel(const float* __restrict__ depth,
+                                                       float* __restrict__ pyr, HizLayout lay,
+                                                       int tile_levels) {
+    __shared__ float lds[2][16 * 16];
+    const int W = lay.w[0], H = lay.h[0];
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    const int x0 = blockIdx.x * kTile + tx * 4;
+    const int y0 = blockIdx.y * kTile + ty * 4;
+    float p[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) p[r][c] = depth_at(depth, W, H, x0 + c, y0 + r);
+    // level 1: 2 x 2 texels per thread
+    float m1[2][2];
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+            m1[b][a] = fminf(fminf(p[2 * b][2 * a], p[2 * b][2 * a + 1]),
+                             fminf(p[2 * b + 1][2 * a], p[2 * b + 1][2 * a + 1]));
+    {
+        const int lx = x0 / 2, ly = y0 / 2;
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+                if (lx + a < lay.w[1] && ly + b < lay.h[1])
+                    pyr[lay.offset[1] + static_cast<int64_t>(ly + b) * lay.w[1] + lx + a] = m1[b][a];
+    }
+    if (tile_levels < 2) return;
+    const float m2 = fminf(fminf(m1[0][0], m1[0][1]), fminf(m1[1][0], m1[1][1]));
+    {
+        const int lx = x0 / 4, ly = y0 / 4;
+        if (lx < lay.w[2] && ly < lay.h[2])
+            pyr[lay.offset[2] + static_cast<int64_t>(ly) * lay.w[2] + lx] = m2;
+    }
+    lds[0][ty * 16 + tx] = m2;
+    int n = 16;  // current level's tile width in texels
+    int cur = 0;
+    for (int L = 3; L <= tile_levels; ++L) {
+        __syncthreads();
+        const int m = n / 2;
+        if (static_cast<int>(threadIdx.x) < m * m) {
+            const int a = threadIdx.x % m, b = threadIdx.x / m;
+            const float* s = lds[cur];
+            const float v = fminf(fminf(s[(2 * b) * n + 2 * a], s[(2 * b) * n + 2 * a + 1]),
+                                  fminf(s[(2 * b + 1) * n + 2 * a], s[(2 * b + 1) * n + 2 * a + 1]));
+            lds[cur ^ 1][b * m + a] = v;
+            const int lx = blockIdx.x * (kTile >> L) + a, ly = blockIdx.y * (kTile >> L) + b;
+            if (lx < lay.w[L] && ly < lay.h[L])
+                pyr[lay.offset[L] + static_cast<int64_t>(ly) * lay.w[L] + lx] = v;
+        }
+        cur ^= 1;
+        n = m;
+    }
+}
+
+// One level from the level below it (global memory), for any level >= 1.
+__global__ void hiz_level_kernel(const float* __restrict__ src, int sw, int sh,
+                                 float* __restrict__ dst, int dw, int dh) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= dw * dh) return;
+    const int x = i % dw, y = i / dw;
+    float v = src[(2 * y) * sw + 2 * x];
+    if (2 * x + 1 < sw) v = fminf(v, src[(2 * y) * sw + 2 * x + 1]);
+    if (2 * y + 1 < sh) {
+        v = fminf(v, src[(2 * y + 1) * sw + 2 * x]);
+        if (2 * x + 1 < sw) v = fminf(v, src[(2 * y + 1) * sw + 2 * x + 1]);
+    }
+    dst[i] = v;
+}
+
+constexpr int kTopLdsFloats = 16384;  // 64 KB of LDS for the levels above the tile pass
+
+// All levels above `first - 1` in one workgroup, ping-ponging through LDS.
+__global__ __launch_bounds__(1024) void hiz_top_kernel(float* __restrict__ pyr, HizLayout lay,
+                                                       int first) {
+    extern __shared__ float lds[];
+    const int sw0 = lay.w[first - 1], sh0 = lay.h[first - 1];
+    float* a = lds;
+    float* b = lds + sw0 * sh0;
+    for (int i = threadIdx.x; i < sw0 * sh0; i += blockDim.x) a[i] = pyr[lay.offset[first - 1] + i];
+    for (int L = first; L < lay.levels; ++L) {
+        __syncthreads();
+        const int sw = lay.w[L - 1], sh = lay.h[L - 1], dw = lay.w[L], dh = lay.h[L];
+        for (int i = threadIdx.x; i < dw * dh; i += blockDim.x) {
+            const int x = i % dw, y = i / dw;
+            float v = a[(2 * y) * sw + 2 * x];
+            if (2 * x + 1 < sw) v = fminf(v, a[(2 * y) * sw + 2 * x + 1]);
+            if (2 * y + 1 < sh) {
+                v = fminf(v, a[(2 * y + 1) * sw + 2 * x]);
+                if (2 * x + 1 < sw) v = fminf(v, a[(2 * y + 1) * sw + 2 * x + 1]);
+            }
+            b[i] = v;
+            pyr[lay.offset[L] + i] = v;
+        }
+        float* t = a;
+        a = b;
+        b = t;
+    }
+}
+
+hipError_t launch_hiz(const float* depth, const HizLayout& lay, float* pyramid,
+                      hipStream_t stream) {
+    const int top = lay.levels - 1;
+    if (top == 0) return hipSuccess;
+    const int tile_levels = top < kTileLevels ? top : kTileLevels;
+    const dim3 grid((lay.w[0] + kTile - 1) / kTile, (lay.h[0] + kTile - 1) / kTile);
+    hipLaunchKernelGGL(hiz_tile_kernel, grid, dim3(256), 0, stream, depth, pyramid, lay,
+                       tile_levels);
+    if (top > kTileLevels) {
+        const int first = kTileLevels + 1;
+        const int64_t need = static_cast<int64_t>(lay.w[first - 1]) * lay.h[first - 1] +
+                             static_cast<int64_t>(lay.w[first]) * lay.h[first];
+        if (need <= kTopLdsFloats) {
+            hipLaunchKernelGGL(hiz_top_kernel, dim3(1), dim3(1024), need * sizeof(float), stream,
+                               pyramid, lay, first);
+        } else {
+            for (int L = first; L <= top; ++L) {
+                const int n = lay.w[L] * lay.h[L];
+                hipLaunchKernelGGL(hiz_level_kernel, dim3((n + 255) / 256), dim3(256), 0, stream,
+                                   pyramid + lay.offset[L - 1], lay.w[L - 1], lay.h[L - 1],
+                                   pyramid + lay.offset[L], lay.w[L], lay.h[L]);
+            }
+        }
+    }
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ Philox --
+
+__global__ void philox_kernel(const uint4* __restrict__ ctr, const uint2* __restrict__ key,
+                              int64_t n, uint4* __restrict__ out) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint2 k = key[i];
+    out[i] = philox4x32_10(ctr[i], k.x, k.y);
+}
+
+hipError_t launch_philox(const uint32_t* ctr, const uint32_t* key, int64_t n, uint32_t* out,
+                         hipStream_t stream) {
+    const int64_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(philox_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, stream,
+                       reinterpret_cast<const uint4*>(ctr), reinterpret_cast<const uint2*>(key), n,
+                       reinterpret_cast<uint4*>(out));
+    return hipGetLastError();
+}
+
+}  // namespace ssr

@@ -1,0 +1,253 @@
+"""Python binding of the C-ABI in ``include/ssr.h`` (argument marshalling only).
+
+Every step of the shading path runs in the HIP library ``libssr.so``; this
+module converts torch device tensors and plain Python values to the C
+structures and raises ``SSRError`` on a non-OK status.  There is no
+fallback: if the library is missing, importing this module fails.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libssr.so")
+
+F32, F16, BF16 = 0, 1, 2
+MARCH_LINEAR, MARCH_HIZ = 0, 1
+NO_DIRECT, NO_SPECULAR = 1, 2
+HIT_OFFSCREEN, HIT_INVALID, HIT_BACKGROUND, HIT_CAP, HIT_SKIPPED = -1, -2, -3, -4, -5
+
+SYMBOLS = ("ssr_ctx_create", "ssr_ctx_destroy", "ssr_shade", "ssr_env_mips_floats",
+           "ssr_env_build_mips", "ssr_hiz_floats", "ssr_hiz_build", "ssr_philox4x32_10",
+           "ssr_status_string")
+
+
+class SSRError(RuntimeError):
+    def __init__(self, status, what):
+        super().__init__(f"{what}: {status_string(status)} ({status})")
+        self.status = status
+
+
+class Camera(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("pos", ctypes.c_float * 3), ("rot", ctypes.c_float * 9),
+                ("fx", ctypes.c_float), ("fy", ctypes.c_float), ("cx", ctypes.c_float),
+                ("cy", ctypes.c_float), ("z_near", ctypes.c_float)]
+
+
+class GBuffer(ctypes.Structure):
+    _fields_ = [("depth", ctypes.c_void_p), ("normal_rough", ctypes.c_void_p),
+                ("albedo_metal", ctypes.c_void_p), ("radiance", ctypes.c_void_p),
+                ("dtype", ctypes.c_int32), ("hiz", ctypes.c_void_p)]
+
+
+class Env(ctypes.Structure):
+    _fields_ = [("rgb", ctypes.c_void_p), ("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("mips", ctypes.c_void_p)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("spp", ctypes.c_int32), ("march", ctypes.c_int32), ("max_steps", ctypes.c_int32),
+                ("step_len", ctypes.c_float), ("max_dist", ctypes.c_float),
+                ("thickness", ctypes.c_float), ("seed", ctypes.c_uint64),
+                ("frame", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
+
+
+def _load():
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(f"{_LIB_PATH} is missing: build it with `python -m paper_2504_01358_amd.build`")
+    lib = ctypes.CDLL(_LIB_PATH)
+    P = ctypes.POINTER
+    vp = ctypes.c_void_p
+    lib.ssr_ctx_create.argtypes = [ctypes.c_int, P(vp)]
+    lib.ssr_ctx_create.restype = ctypes.c_int
+    lib.ssr_ctx_destroy.argtypes = [vp]
+    lib.ssr_ctx_destroy.restype = None
+    lib.ssr_shade.argtypes = [vp, P(Camera), P(GBuffer), P(Env), P(Params), vp, vp, vp, vp]
+    lib.ssr_shade.restype = ctypes.c_int
+    lib.ssr_env_mips_floats.argtypes = [ctypes.c_int32, ctypes.c_int32]
+    lib.ssr_env_mips_floats.restype = ctypes.c_int64
+    lib.ssr_env_build_mips.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, vp, vp]
+    lib.ssr_env_build_mips.restype = ctypes.c_int
+    lib.ssr_hiz_floats.argtypes = [ctypes.c_int32, ctypes.c_int32]
+    lib.ssr_hiz_floats.restype = ctypes.c_int64
+    lib.ssr_hiz_build.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, vp, vp]
+    lib.ssr_hiz_build.restype = ctypes.c_int
+    lib.ssr_philox4x32_10.argtypes = [vp, vp, ctypes.c_int64, vp, vp]
+    lib.ssr_philox4x32_10.restype = ctypes.c_int
+    lib.ssr_status_string.argtypes = [ctypes.c_int]
+    lib.ssr_status_string.restype = ctypes.c_char_p
+    return lib
+
+
+lib = _load()
+
+
+def status_string(status: int) -> str:
+    return lib.ssr_status_string(int(status)).decode()
+
+
+def _check(status, what):
+    if status != 0:
+        raise SSRError(status, what)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream, device):
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev_tensor(t, name, dtype=None, shape=None):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return t
+
+
+_GBUF_DTYPES = {torch.float32: F32, torch.float16: F16, torch.bfloat16: BF16}
+
+
+def make_camera(cam: dict) -> Camera:
+    c = Camera()
+    c.width, c.height = int(cam["width"]), int(cam["height"])
+    for k, v in enumerate(list(map(float, cam["pos"]))):
+        c.pos[k] = v
+    rot = [float(v) for row in cam["rot"] for v in (row if hasattr(row, "__len__") else [row])]
+    for k, v in enumerate(rot):
+        c.rot[k] = v
+    c.fx, c.fy, c.cx, c.cy = (float(cam[k]) for k in ("fx", "fy", "cx", "cy"))
+    c.z_near = float(cam["z_near"])
+    return c
+
+
+def make_params(p: dict) -> Params:
+    q = Params()
+    q.spp, q.march, q.max_steps = int(p["spp"]), int(p["march"]), int(p["max_steps"])
+    q.step_len, q.max_dist, q.thickness = (float(p[k]) for k in ("step_len", "max_dist", "thickness"))
+    q.seed = int(p["seed"]) & 0xFFFFFFFFFFFFFFFF
+    q.frame = int(p.get("frame", 0)) & 0xFFFFFFFF
+    q.flags = int(p.get("flags", 0))
+    return q
+
+
+class Context:
+    """Owns an ``ssr_ctx`` (per-device workspace) for one device."""
+
+    def __init__(self, device=0):
+        self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
+        h = ctypes.c_void_p()
+        _check(lib.ssr_ctx_create(self.device.index or 0, ctypes.byref(h)), "ssr_ctx_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib.ssr_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def shade(self, camera, depth, normal_rough, albedo_metal, radiance, env, params,
+              env_mips=None, hiz=None, out=None, hits=None, steps=None, stream=None):
+        """Shade one frame; returns ``out`` [H][W][3] float32 (and fills the
+        optional int32 ``hits`` / ``steps`` [H][W][spp] tensors).  ``env_mips``
+        and ``hiz`` optionally supply prebuilt pyramids for these inputs."""
+        cam = camera if isinstance(camera, Camera) else make_camera(camera)
+        prm = params if isinstance(params, Params) else make_params(params)
+        H, W = cam.height, cam.width
+        _dev_tensor(depth, "depth", torch.float32, (H, W))
+        dt = normal_rough.dtype
+        if dt not in _GBUF_DTYPES:
+            raise TypeError(f"unsupported G-buffer dtype {dt}")
+        for name, t in (("normal_rough", normal_rough), ("albedo_metal", albedo_metal),
+                        ("radiance", radiance)):
+            _dev_tensor(t, name, dt, (H, W, 4))
+        _dev_tensor(env, "env", torch.float32)
+        if env.dim() != 3 or env.shape[2] != 3:
+            raise ValueError("env must be [He][We][3]")
+        if env_mips is not None:
+            _dev_tensor(env_mips, "env_mips", torch.float32)
+            if env_mips.numel() != env_mips_floats(env.shape[1], env.shape[0]):
+                raise ValueError("env_mips has the wrong size for this env")
+        if out is None:
+            out = torch.empty((H, W, 3), dtype=torch.float32, device=depth.device)
+        _dev_tensor(out, "out", torch.float32, (H, W, 3))
+        for name, t in (("hits", hits), ("steps", steps)):
+            if t is not None:
+                _dev_tensor(t, name, torch.int32, (H, W, prm.spp))
+        if hiz is not None:
+            _dev_tensor(hiz, "hiz", torch.float32)
+            if hiz.numel() != hiz_floats(W, H):
+                raise ValueError("hiz has the wrong size for this depth buffer")
+        g = GBuffer(depth.data_ptr(), normal_rough.data_ptr(), albedo_metal.data_ptr(),
+                    radiance.data_ptr(), _GBUF_DTYPES[dt],
+                    None if hiz is None or hiz.numel() == 0 else hiz.data_ptr())
+        e = Env(env.data_ptr(), int(env.shape[1]), int(env.shape[0]),
+                None if env_mips is None else env_mips.data_ptr())
+        st = lib.ssr_shade(self._h, ctypes.byref(cam), ctypes.byref(g), ctypes.byref(e),
+                           ctypes.byref(prm), _ptr(out), _ptr(hits), _ptr(steps),
+                           _stream(stream, depth.device))
+        _check(st, "ssr_shade")
+        return out
+
+
+def env_mips_floats(width, height) -> int:
+    return int(lib.ssr_env_mips_floats(int(width), int(height)))
+
+
+def env_build_mips(env, out=None, stream=None):
+    """Mip chain of an equirect env ``[He][We][3]`` (library layout, float32)."""
+    _dev_tensor(env, "env", torch.float32)
+    n = env_mips_floats(env.shape[1], env.shape[0])
+    if n == 0:
+        raise SSRError(-1, "env_build_mips: env must be [He][2He][3] with He a power of two")
+    if out is None:
+        out = torch.empty(n, dtype=torch.float32, device=env.device)
+    _check(lib.ssr_env_build_mips(_ptr(env), int(env.shape[1]), int(env.shape[0]), _ptr(out),
+                                  _stream(stream, env.device)), "ssr_env_build_mips")
+    return out
+
+
+def hiz_floats(width, height) -> int:
+    return int(lib.ssr_hiz_floats(int(width), int(height)))
+
+
+def hiz_build(depth, out=None, stream=None):
+    """Levels 1..top of the min-depth pyramid of ``depth`` [H][W] (flat float32)."""
+    _dev_tensor(depth, "depth", torch.float32)
+    H, W = depth.shape
+    n = hiz_floats(W, H)
+    if out is None:
+        out = torch.empty(max(n, 1), dtype=torch.float32, device=depth.device)
+    _check(lib.ssr_hiz_build(_ptr(depth), W, H, _ptr(out), _stream(stream, depth.device)),
+           "ssr_hiz_build")
+    return out[:n]
+
+
+def philox4x32_10(ctr, key, out=None, stream=None):
+    """Philox4x32-10 of ``ctr`` [n][4] under ``key`` [n][2] (int32 tensors
+    holding the uint32 bit patterns)."""
+    _dev_tensor(ctr, "ctr", torch.int32)
+    _dev_tensor(key, "key", torch.int32)
+    n = ctr.shape[0]
+    if out is None:
+        out = torch.empty((n, 4), dtype=torch.int32, device=ctr.device)
+    _check(lib.ssr_philox4x32_10(_ptr(ctr), _ptr(key), n, _ptr(out), _stream(stream, ctr.device)),
+           "ssr_philox4x32_10")
+    return out

@@ -1,0 +1,94 @@
+"""Helpers for the GPU tests: upload inputs, run the library, run the oracle,
+compare the two."""
+
+import numpy as np
+import torch
+
+import oracle
+from scenes import quantise_gbuffer
+
+BUFS = ("normal_rough", "albedo_metal", "radiance")
+
+
+def f32_camera(cam):
+    """Round every camera value to float32 (what the library sees)."""
+    out = dict(cam)
+    out["pos"] = np.asarray(cam["pos"], np.float32)
+    out["rot"] = np.asarray(cam["rot"], np.float32).reshape(3, 3)
+    for k in ("fx", "fy", "cx", "cy", "z_near"):
+        out[k] = np.float32(cam[k])
+    return out
+
+
+def f32_gbuf(g):
+    return {k: np.ascontiguousarray(np.asarray(v, np.float32)) for k, v in g.items()}
+
+
+def gbuf_of(scene):
+    return dict(depth=scene.depth, normal_rough=scene.normal_rough,
+                albedo_metal=scene.albedo_metal, radiance=scene.radiance)
+
+
+def run_gpu(ctx, cam, g, env, params, dtype="f32", want_hits=True, want_steps=True,
+            env_mips=None, hiz=None):
+    """Shade on cuda:0.  Returns numpy out/hits/steps and the G-buffer values
+    the GPU actually read (quantised for f16/bf16)."""
+    dev = torch.device("cuda", 0)
+    W, H, S = int(cam["width"]), int(cam["height"]), int(params["spp"])
+    depth = torch.from_numpy(np.ascontiguousarray(g["depth"], np.float32)).to(dev)
+    seen = dict(depth=np.asarray(g["depth"], np.float32))
+    if dtype == "f32":
+        bufs = {k: torch.from_numpy(np.ascontiguousarray(g[k], np.float32)).to(dev) for k in BUFS}
+        for k in BUFS:
+            seen[k] = np.asarray(g[k], np.float32)
+    else:
+        class _S:
+            pass
+        s = _S()
+        for k in BUFS:
+            setattr(s, k, np.asarray(g[k], np.float32))
+        bits, vals = quantise_gbuffer(s, dtype)
+        tdt = torch.float16 if dtype == "f16" else torch.bfloat16
+        bufs = {k: torch.from_numpy(bits[k].view(np.int16)).to(dev).view(tdt) for k in BUFS}
+        seen.update(vals)
+    envt = torch.from_numpy(np.ascontiguousarray(env, np.float32)).to(dev)
+    hits = torch.full((H, W, S), -99, dtype=torch.int32, device=dev) if want_hits else None
+    steps = torch.full((H, W, S), -99, dtype=torch.int32, device=dev) if want_steps else None
+    out = ctx.shade(cam, depth, bufs["normal_rough"], bufs["albedo_metal"], bufs["radiance"],
+                    envt, params, env_mips=env_mips, hiz=hiz, hits=hits, steps=steps)
+    torch.cuda.synchronize()
+    res = dict(out=out.cpu().numpy().astype(np.float64))
+    if want_hits:
+        res["hits"] = hits.cpu().numpy().astype(np.int64)
+    if want_steps:
+        res["steps"] = steps.cpu().numpy().astype(np.int64)
+    return res, seen
+
+
+def oracle_frame(cam, g, env, params):
+    return oracle.shade_frame(cam, g, env, params)
+
+
+def rel_err(gpu, ref, floor=1e-6):
+    return np.abs(gpu - ref) / np.maximum(np.abs(ref), floor)
+
+
+def compare(gpu_out, gpu_hits, ref_out, ref_hits, label=""):
+    """Hit agreement over valid samples and per-pixel error on pixels whose
+    samples all agree.  Returns a dict of statistics (printed)."""
+    valid = ref_hits != oracle.shade.HIT_BACKGROUND
+    agree = (gpu_hits == ref_hits)
+    frac = agree[valid].mean() if valid.any() else 1.0
+    pix_ok = agree.all(axis=-1)
+    rel = rel_err(gpu_out, ref_out).max(axis=-1)
+    r = rel[pix_ok]
+    stats = dict(samples=int(valid.sum()), hit_agreement=float(frac),
+                 pixels_compared=int(pix_ok.sum()), pixels=int(pix_ok.size),
+                 rel_p50=float(np.quantile(r, 0.5)) if r.size else 0.0,
+                 rel_p99=float(np.quantile(r, 0.99)) if r.size else 0.0,
+                 rel_p999=float(np.quantile(r, 0.999)) if r.size else 0.0,
+                 rel_max=float(r.max()) if r.size else 0.0,
+                 frac_within_1e4=float((r <= 1e-4).mean()) if r.size else 1.0)
+    print(f"[{label}] " + " ".join(f"{k}={v:.6g}" if isinstance(v, float) else f"{k}={v}"
+                                   for k, v in stats.items()), flush=True)
+    return stats

@@ -1,0 +1,113 @@
+"""The C-ABI library without a GPU: it loads, exports every function that
+include/ssr.h declares, its structures have the layout the binding assumes,
+and the host-only paths (sizes, status strings, argument checks that return
+before touching a device) behave as documented."""
+
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ssr.h")
+LIB = os.path.join(ROOT, "paper_2504_01358_amd", "libssr.so")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        import importlib.util
+        spec = importlib.util.spec_from_file_location(
+            "_b", os.path.join(ROOT, "paper_2504_01358_amd", "build.py"))
+        m = importlib.util.module_from_spec(spec)
+        spec.loader.exec_module(m)
+        m.build()
+    from paper_2504_01358_amd import ssr
+    return ssr
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ssr_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert len(names) == 9, names
+    raw = ctypes.CDLL(LIB)
+    for n in names:
+        assert hasattr(raw, n), n
+    assert set(names) == set(lib.SYMBOLS)
+
+
+def test_struct_layout_matches_header(lib, tmp_path):
+    src = tmp_path / "layout.c"
+    fields = {
+        "ssr_camera": ["width", "height", "pos", "rot", "fx", "fy", "cx", "cy", "z_near"],
+        "ssr_gbuffer": ["depth", "normal_rough", "albedo_metal", "radiance", "dtype", "hiz"],
+        "ssr_env": ["rgb", "width", "height", "mips"],
+        "ssr_params": ["spp", "march", "max_steps", "step_len", "max_dist", "thickness", "seed",
+                       "frame", "flags"],
+    }
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ssr.h"', "int main(void){"]
+    for s, fs in fields.items():
+        lines.append(f'printf("{s} size %zu\\n", sizeof({s}));')
+        for f in fs:
+            lines.append(f'printf("{s} {f} %zu\\n", offsetof({s}, {f}));')
+    lines.append("return 0;}")
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)], check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n"):
+        if line:
+            a, b, c = line.split()
+            got[(a, b)] = int(c)
+    py = {"ssr_camera": lib.Camera, "ssr_gbuffer": lib.GBuffer, "ssr_env": lib.Env,
+          "ssr_params": lib.Params}
+    for s, cls in py.items():
+        assert got[(s, "size")] == ctypes.sizeof(cls), s
+        for f in fields[s]:
+            assert got[(s, f)] == getattr(cls, f).offset, (s, f)
+
+
+def test_sizes_and_status_strings(lib):
+    # env mip chain: levels He x 2He down to 1 x 2, four floats per texel
+    assert lib.env_mips_floats(512, 256) == 4 * sum((512 >> k) * (256 >> k) for k in range(9))
+    assert lib.env_mips_floats(2, 1) == 8
+    for bad in ((512, 255), (500, 250), (256, 256), (0, 0), (2 * 16384, 16384)):
+        assert lib.env_mips_floats(*bad) == 0
+    # min pyramid, levels 1..top with ceil halving
+    def hiz(w, h):
+        n = 0
+        while w > 1 or h > 1:
+            w, h = (w + 1) // 2, (h + 1) // 2
+            n += w * h
+        return n
+    for w, h in ((1920, 1080), (1, 1), (7, 3), (3840, 2160), (16384, 1)):
+        assert lib.hiz_floats(w, h) == hiz(w, h)
+    assert lib.hiz_floats(0, 5) == 0 and lib.hiz_floats(16385, 2) == 0
+    for s in (0, -1, -2, -3, -4, -5):
+        assert lib.status_string(s) and lib.status_string(s) != "unknown status"
+    assert lib.status_string(-99) == "unknown status"
+
+
+def test_host_side_argument_checks(lib):
+    raw = lib.lib
+    cam = lib.Camera()
+    g = lib.GBuffer()
+    e = lib.Env()
+    p = lib.Params()
+    byref = ctypes.byref
+    # null context / structures: rejected before any device work
+    assert raw.ssr_shade(None, byref(cam), byref(g), byref(e), byref(p), None, None, None, None) == -1
+    assert raw.ssr_env_build_mips(None, 512, 256, None, None) == -1
+    assert raw.ssr_hiz_build(None, 16, 16, None, None) == -1
+    assert raw.ssr_philox4x32_10(None, None, 0, None, None) == 0
+    assert raw.ssr_philox4x32_10(None, None, 5, None, None) == -1
+    assert raw.ssr_philox4x32_10(None, None, -1, None, None) == -1
+    assert raw.ssr_ctx_create(0, None) == -1
+    raw.ssr_ctx_destroy(None)

@@ -14,6 +14,8 @@ import pytest
 
 from oracle import brdf, camera, env, march, philox, shade
 
+from closed_form import floor_wall_scene, open_floor
+
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 
@@ -339,35 +341,8 @@ def test_linear_march_wall_closed_form():
 
 # -------------------------------------------------- closed-form scenes ---
 
-def _floor_wall_scene(w=64, h=64, wall_z=-6.0, cam_h=1.0):
-    """Camera at height cam_h looking along -z at a mirror floor y=0 and a
-    fronto-parallel wall z=wall_z.  G-buffers by exact ray casting here."""
-    cam = dict(width=w, height=h, pos=np.array([0.0, cam_h, 0.0]),
-               rot=np.array([[1.0, 0, 0], [0, 1.0, 0], [0, 0, -1.0]]),
-               fx=w * 0.8, fy=w * 0.8, cx=w / 2, cy=h / 2, z_near=0.01)
-    c = camera.unpack(cam)
-    jj, ii = np.meshgrid(np.arange(h, dtype=float), np.arange(w, dtype=float), indexing="ij")
-    x = (ii + 0.5 - c["cx"]) / c["fx"]
-    y = -(jj + 0.5 - c["cy"]) / c["fy"]
-    t_floor = np.where(y < 0, -cam_h / np.where(y < 0, y, -1), np.inf)
-    t_wall = -wall_z
-    is_floor = t_floor < t_wall
-    depth = np.where(is_floor, t_floor, t_wall)
-    nr = np.zeros((h, w, 4))
-    am = np.zeros((h, w, 4))
-    nr[is_floor] = [0, 1, 0, 0.0]            # mirror floor
-    am[is_floor] = [1, 1, 1, 1.0]
-    nr[~is_floor] = [0, 0, 1, 0.7]           # rough dielectric wall
-    am[~is_floor] = [0.5, 0.5, 0.5, 0.0]
-    rad = np.zeros((h, w, 4))
-    rad[..., 0] = np.arange(h * w).reshape(h, w) + 1.0   # identifies the pixel
-    rad[..., 1] = 1.0
-    rad[..., 2] = 2.0
-    return cam, dict(depth=depth, normal_rough=nr, albedo_metal=am, radiance=rad), is_floor
-
-
 def test_mirror_floor_hits_wall_at_closed_form_pixel():
-    cam, g, is_floor = _floor_wall_scene()
+    cam, g, is_floor = floor_wall_scene()
     c = camera.unpack(cam)
     W, H = c["W"], c["H"]
     envmap = np.full((8, 16, 3), 0.25)
@@ -401,22 +376,10 @@ def test_mirror_floor_hits_wall_at_closed_form_pixel():
     assert checked > 300
 
 
-def _open_floor(w=48, h=32, rough=0.0, metal=1.0, albedo=1.0):
-    """Camera looking down at an unbounded floor and nothing else."""
-    cam = dict(width=w, height=h, pos=np.array([0.0, 3.0, 0.0]),
-               rot=np.array([[1.0, 0, 0], [0, 0, -1.0], [0, -1.0, 0]]),
-               fx=w * 0.6, fy=w * 0.6, cx=w / 2, cy=h / 2, z_near=0.01)
-    depth = np.full((h, w), 3.0)
-    nr = np.tile([0, 1.0, 0, rough], (h, w, 1))
-    am = np.tile([albedo, albedo, albedo, metal], (h, w, 1))
-    rad = np.tile([5.0, 6.0, 7.0, 0], (h, w, 1))
-    return cam, dict(depth=depth, normal_rough=nr, albedo_metal=am, radiance=rad)
-
-
 def test_white_furnace():
     """Uniform environment L, specular off, dielectric: out = a * L exactly."""
     L = 1.75
-    cam, g = _open_floor(metal=0.0, rough=0.4)
+    cam, g = open_floor(metal=0.0, rough=0.4)
     rng = np.random.default_rng(9)
     g["albedo_metal"][..., :3] = rng.uniform(0, 1, g["albedo_metal"][..., :3].shape)
     g["normal_rough"][..., 3] = rng.uniform(0, 1, g["normal_rough"][..., 3].shape)
@@ -434,7 +397,7 @@ def test_mirror_furnace():
     """Perfect mirror (a = 1, m = 1, rho = 0) over an open floor under a
     uniform environment: every ray leaves the screen and out = L exactly."""
     L = 2.5
-    cam, g = _open_floor()
+    cam, g = open_floor()
     envmap = np.full((16, 32, 3), L)
     params = dict(spp=2, march=1, max_steps=64, step_len=0.125, max_dist=100.0,
                   thickness=0.05, seed=3, frame=0, flags=0)
@@ -448,7 +411,7 @@ def test_rough_furnace_equals_directional_albedo():
     pixel mean over many samples converges to L * int f_s cos (quadrature)."""
     L = 1.0
     alpha = 0.5
-    cam, g = _open_floor(w=8, h=8, rough=alpha, metal=1.0, albedo=0.8)
+    cam, g = open_floor(w=8, h=8, rough=alpha, metal=1.0, albedo=0.8)
     envmap = np.full((16, 32, 3), L)
     params = dict(spp=4096, march=1, max_steps=64, step_len=0.125, max_dist=100.0,
                   thickness=0.05, seed=12, frame=0, flags=0)
@@ -464,7 +427,7 @@ def test_rough_furnace_equals_directional_albedo():
 
 
 def test_background_reads_environment():
-    cam, g = _open_floor(w=8, h=8)
+    cam, g = open_floor(w=8, h=8)
     g["depth"][:] = np.inf
     rng = np.random.default_rng(2)
     envmap = rng.uniform(1, 2, (8, 16, 3))
