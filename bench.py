@@ -38,6 +38,9 @@ def parse():
     ap.add_argument("--no-variants", action="store_true", help="FP32 only")
     ap.add_argument("--cpu-rows", type=int, default=0,
                     help="oracle sample: every k-th row (default 8)")
+    ap.add_argument("--copy-reference", action="store_true",
+                    help="also run one plain device copy of 256 MiB (the reference for "
+                         "scaling hardware byte counters)")
     return ap.parse_args()
 
 
@@ -74,9 +77,11 @@ def algorithmic_bytes(scene, hits, steps, dtype):
     valid &= hits != -5
     n_hit = int((hits >= 0).sum())
     n_env = int(valid.sum()) - n_hit
-    shade = P * (bg + 12) + 4 * n_iter + br_hit * n_hit + 12 * n_env
-    hiz = P * 4 + 4 * int(sum(math.ceil(scene.width / 2 ** k) * math.ceil(scene.height / 2 ** k)
-                              for k in range(1, 13)))
+    per_iter = 8 if scene.params["march"] == 1 else 4
+    shade = P * (bg + 12) + per_iter * n_iter + br_hit * n_hit + 12 * n_env
+    texels = sum(math.ceil(scene.width / 2 ** k) * math.ceil(scene.height / 2 ** k)
+                 for k in range(0, 15))
+    hiz = P * 4 + 8 * int(texels)
     return shade, hiz, dict(mean_iters=n_iter / max(1, int(valid.sum())), hit_frac=n_hit / hits.size)
 
 
@@ -144,7 +149,8 @@ def _oracle_rows(args):
     g = dict(depth=sc.depth, normal_rough=sc.normal_rough, albedo_metal=sc.albedo_metal,
              radiance=sc.radiance)
     mips = oracle.env.build_mips(sc.env)
-    pyr = oracle.march.hiz_pyramid(sc.depth) if sc.params["march"] == 1 else None
+    pyr = ((oracle.march.hiz_pyramid(sc.depth), oracle.march.hiz_max_pyramid(sc.depth))
+           if sc.params["march"] == 1 else None)
     t0 = time.perf_counter()
     n = 0
     for r in rows:
@@ -206,6 +212,17 @@ def main():
         for dt in ("f16", "bf16"):
             res[dt] = time_gpu(ctx, scene, dt, args.steps, args.warmup, dev, mips)
             print(f"bench: {dt} {res[dt]['ms_per_step']:.3f} ms/frame", file=sys.stderr, flush=True)
+    if args.copy_reference:
+        # 256 MiB read + 256 MiB written; 1 GiB written in between pushes the
+        # source out of the 256 MB Infinity Cache so its reads reach HBM
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        flush = torch.empty(256 << 20, dtype=torch.float32, device=dev)
+        flush.fill_(2.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst, flush
     rays = scene.width * scene.height * scene.params["spp"]
     r32 = res["f32"]
     achieved = r32["bytes_shade"] / (r32["shade_ms"] * 1e-3) / 1e9

@@ -64,8 +64,9 @@ typedef enum {
 typedef enum { SSR_F32 = 0, SSR_F16 = 1, SSR_BF16 = 2 } ssr_dtype;
 
 /* March modes.  LINEAR: fixed world-space steps (Appendix D, Algorithm 1).
- * HIZ: exact first hit on the depth heightfield, traversed over a min-depth
- * pyramid with at most max_steps iterations. */
+ * HIZ: exact first hit on the depth heightfield, traversed over a min-max
+ * depth pyramid with at most max_steps iterations (skip a cell the ray passes
+ * wholly in front of or wholly behind, descend, or test a pixel: one each). */
 enum { SSR_MARCH_LINEAR = 0, SSR_MARCH_HIZ = 1 };
 
 /* Flags: drop the direct diffuse term, or the Monte-Carlo specular term. */
@@ -90,17 +91,17 @@ typedef struct {
 } ssr_camera;
 
 typedef struct {
-    const float* depth;       /* [H][W] float32 view-space linear depth; +inf (or
-                                 any non-finite value) marks background; no NaN  */
+    const float* depth;       /* [H][W] float32 view-space linear depth, > 0;
+                                 +inf marks background; no NaN                   */
     const void* normal_rough; /* [H][W][4] (n.x, n.y, n.z, roughness), world n,
                                  need not be unit length but must be non-zero   */
     const void* albedo_metal; /* [H][W][4] (a.r, a.g, a.b, metallic)             */
     const void* radiance;     /* [H][W][4] (c1.r, c1.g, c1.b, unused): the
                                  first-pass radiance read at hit pixels         */
     int32_t dtype;            /* ssr_dtype of the three [H][W][4] buffers        */
-    const float* hiz;         /* NULL, or levels 1..top of this depth buffer's
-                                 min pyramid as ssr_hiz_build wrote them (then
-                                 ssr_shade does not build it)                   */
+    const float* hiz;         /* NULL, or this depth buffer's min-max pyramid as
+                                 ssr_hiz_build wrote it (then ssr_shade does
+                                 not build it)                                   */
 } ssr_gbuffer;
 
 typedef struct {
@@ -125,7 +126,7 @@ typedef struct {
 } ssr_params;
 
 /* Create a context on HIP device `device` (must be gfx950).  The context owns
- * a grow-only workspace (min-depth pyramid, env mip chain).  *out is set to
+ * a grow-only workspace (min-max depth pyramid, env mip chain).  *out is set to
  * NULL on failure. */
 int ssr_ctx_create(int device, ssr_ctx** out);
 
@@ -140,7 +141,7 @@ void ssr_ctx_destroy(ssr_ctx* ctx);
  * Sample s of pixel q = j*W + i draws Philox4x32-10 with counter
  * (q, s, frame, 0): u1 = (x0 >> 8) 2^-24 picks the azimuth, u2 = (x1 >> 8) 2^-24
  * the cap height of the visible-normal sample.  width or height 0 is a no-op.
- * In hiz mode the min-depth pyramid is built in the context's workspace unless
+ * In hiz mode the min-max depth pyramid is built in the context's workspace unless
  * gbuf->hiz supplies it; the env mip chain likewise unless env->mips does.
  * Both builds run on `stream` before the shading kernel. */
 int ssr_shade(ssr_ctx* ctx, const ssr_camera* cam, const ssr_gbuffer* gbuf,
@@ -158,15 +159,18 @@ int64_t ssr_env_mips_floats(int32_t width, int32_t height);
 int ssr_env_build_mips(const float* rgb, int32_t width, int32_t height, float* mips,
                        void* stream);
 
-/* Number of floats of levels 1..top of the min-depth pyramid of a W x H depth
- * buffer (0 for an empty or oversized image). */
+/* Number of floats of the min-max depth pyramid of a W x H depth buffer (0 for
+ * an empty or oversized image). */
 int64_t ssr_hiz_floats(int32_t width, int32_t height);
 
-/* Fill `pyramid` with levels 1..top of the min-depth pyramid: level L has
- * ceil(W_{L-1}/2) x ceil(H_{L-1}/2) texels, each the minimum of its existing
- * children, row-major, level after level, ending at 1 x 1.  Level 0 is the
- * depth buffer itself and is not copied.  Pass the buffer to ssr_shade
- * through ssr_gbuffer.hiz to reuse it. */
+/* Fill `pyramid` (ssr_hiz_floats floats) with levels 0..top of the min-max
+ * depth pyramid the hierarchical march traverses, in inverse depth: level 0
+ * is W x H, level L has ceil(W_{L-1}/2) x ceil(H_{L-1}/2) texels and the last
+ * level is 1 x 1.  Each texel is the pair (1/min D, 1/max D) over the pixels it
+ * covers (level 0: (1/D, 1/D); background: 0), the correctly rounded float32
+ * quotients, stored as two floats, row-major, level after level.  Depths must
+ * be positive.  Pass the buffer to ssr_shade through ssr_gbuffer.hiz to reuse
+ * it. */
 int ssr_hiz_build(const float* depth, int32_t width, int32_t height, float* pyramid,
                   void* stream);
 

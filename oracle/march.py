@@ -17,21 +17,32 @@ fixed-step version with a depth-match threshold.  Two marches are defined:
   Samples inside the origin pixel are skipped and never count as in front.
 
 * ``march_hiz``: the same criterion, made exact for the piecewise-constant
-  depth heightfield and accelerated by a min-depth pyramid (the hierarchical
-  tracing that Sec. 3.3 cites).  The view-space ray is clipped to
-  [0, min(max_dist, near-plane crossing)], projected to a screen segment
+  depth heightfield and accelerated by a min-max depth pyramid (the
+  hierarchical tracing that Sec. 3.3 cites).  The view-space ray is clipped
+  to [0, min(max_dist, near-plane crossing)], projected to a screen segment
   P(s) = P0 + s (P1 - P0), s in [0, 1], whose depth 1/((1-s)/d0 + s/d1) is
   monotone in s, and clipped to the screen.  Along the segment the pixels are
   visited in order; in pixel q the ray's depth runs from d_in to d_out.  The
   ray hits q when its depth range meets the slab [D[q], D[q] + thickness]
   and it has been in front of the depth buffer before reaching the slab:
   either in an earlier pixel (lo < D there) or on entering q (d_in < D[q]).
-  The origin pixel never counts.  The traversal visits cells of the pyramid;
-  each iteration does one of: skip the current level-L cell (whole ray
-  interval in front of its minimum depth) and go up one level, go down one
-  level, or test a level-0 pixel.  ``brute_force_first_hit`` scans every
-  pixel the segment crosses, in order, and is what the traversal must
-  reproduce when the iteration cap is lifted.
+  The origin pixel never counts.
+
+  The traversal holds a level L and the level-0 pixel that contains the
+  current point of the segment.  A cell can be skipped when the ray's depth
+  range over the part of the segment inside it lies wholly in front of the
+  cell's minimum depth (the ray is in front of every pixel there) or wholly
+  behind the cell's maximum depth plus the thickness (no slab there can be
+  met).  Each iteration looks at the level-L cell and its parent (level
+  L + 1, below the top):
+    - parent skippable: move to the parent's far boundary, L = L + 1;
+    - else the level-L cell skippable: move to its far boundary;
+    - else, above level 0: L = max(L - 2, 0) (the parent's own parent was
+      already known not to be skippable, so the next pair is two levels
+      down);
+    - else at level 0 test the pixel; on a miss move to the next pixel.
+  ``brute_force_first_hit`` scans every pixel the segment crosses, in order,
+  and is what the traversal must reproduce when the iteration cap is lifted.
 
 Result codes: q >= 0 hit pixel (j*W + i); -1 left the screen or the ray
 segment; -4 iteration cap reached.
@@ -45,21 +56,30 @@ HIT_OFFSCREEN = -1
 HIT_CAP = -4
 
 
+def _reduce_levels(depth, op, pad_value):
+    lv = [np.asarray(depth, np.float64)]
+    while lv[-1].shape != (1, 1):
+        d = lv[-1]
+        h, w = d.shape
+        ph, pw = h + (h & 1), w + (w & 1)
+        pad = np.full((ph, pw), pad_value)
+        pad[:h, :w] = d
+        lv.append(op(pad.reshape(ph // 2, 2, pw // 2, 2), axis=(1, 3)))
+    return lv
+
+
 def hiz_pyramid(depth):
     """Levels 0..top of the min-depth pyramid (level 0 is the depth itself).
 
     Level L has ceil(W_{L-1}/2) x ceil(H_{L-1}/2) texels, each the minimum of
     its (up to four) children; the last level is 1 x 1.
     """
-    lv = [np.asarray(depth, np.float64)]
-    while lv[-1].shape != (1, 1):
-        d = lv[-1]
-        h, w = d.shape
-        ph, pw = h + (h & 1), w + (w & 1)
-        pad = np.full((ph, pw), np.inf)
-        pad[:h, :w] = d
-        lv.append(pad.reshape(ph // 2, 2, pw // 2, 2).min(axis=(1, 3)))
-    return lv
+    return _reduce_levels(depth, np.min, np.inf)
+
+
+def hiz_max_pyramid(depth):
+    """The same levels holding the maximum depth of each cell."""
+    return _reduce_levels(depth, np.max, -np.inf)
 
 
 def march_linear(cam, depth, org_pix, V0, Dv, step_len, max_steps, max_dist, thickness):
@@ -142,15 +162,16 @@ def _ray_depth(d0, d1, s):
 
 
 def march_hiz(cam, pyramid, org_pix, V0, Dv, max_steps, max_dist, thickness):
-    """Hierarchical march over the min pyramid, vectorised in lock step.
+    """Hierarchical march over the min-max pyramid, vectorised in lock step.
 
-    Returns (codes, iterations).  ``max_steps`` caps the iterations (skip,
-    descend and level-0 test each count one).
+    ``pyramid`` is the pair (hiz_pyramid, hiz_max_pyramid) of the depth.
+    Returns (codes, iterations).  ``max_steps`` caps the iterations.
     """
     c = camera.unpack(cam)
     W, H = c["W"], c["H"]
-    top = len(pyramid) - 1
-    depth = pyramid[0]
+    pyr_min, pyr_max = pyramid
+    top = len(pyr_min) - 1
+    depth = pyr_min[0]
     n = V0.shape[0]
     P0, dP, d0, d1, s_max, valid = screen_segment(cam, org_pix, V0, Dv, max_dist)
     codes = np.full(n, HIT_CAP, np.int64)
@@ -162,64 +183,79 @@ def march_hiz(cam, pyramid, org_pix, V0, Dv, max_steps, max_dist, thickness):
     L = np.zeros(n, np.int64)
     ix = org_pix[:, 0].astype(np.int64).copy()
     iy = org_pix[:, 1].astype(np.int64).copy()
+
+    def cell(a, lv):
+        """Bounds, exit parameter and skip tests of the level-lv cells that
+        contain the current pixels of rays a."""
+        size = np.left_shift(1, lv)
+        x0 = (ix[a] >> lv) * size
+        y0 = (iy[a] >> lv) * size
+        x1 = np.minimum(x0 + size, W)
+        y1 = np.minimum(y0 + size, H)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            sx = np.where(dP[a, 0] > 0, (x1 - P0[a, 0]) / dP[a, 0],
+                          np.where(dP[a, 0] < 0, (x0 - P0[a, 0]) / dP[a, 0], np.inf))
+            sy = np.where(dP[a, 1] > 0, (y1 - P0[a, 1]) / dP[a, 1],
+                          np.where(dP[a, 1] < 0, (y0 - P0[a, 1]) / dP[a, 1], np.inf))
+        s_exit = np.minimum(np.minimum(sx, sy), s_max[a])
+        din = _ray_depth(d0[a], d1[a], s[a])
+        dout = _ray_depth(d0[a], d1[a], s_exit)
+        hi = np.maximum(din, dout)
+        lo = np.minimum(din, dout)
+        front = hi < _gather(pyr_min, lv, ix[a], iy[a])        # in front of every pixel
+        behind = lo > _gather(pyr_max, lv, ix[a], iy[a]) + thickness  # behind every slab
+        return dict(x0=x0, y0=y0, x1=x1, y1=y1, sx=sx, sy=sy, s_exit=s_exit, din=din, lo=lo,
+                    front=front, skip=front | behind)
+
     step = 0
     while active.any() and step < max_steps:
         step += 1
         a = np.nonzero(active)[0]
         iters[a] += 1
         La = L[a]
-        size = np.left_shift(1, La)
-        cx0 = (ix[a] >> La) * size
-        cy0 = (iy[a] >> La) * size
-        cx1 = np.minimum(cx0 + size, W)
-        cy1 = np.minimum(cy0 + size, H)
-        with np.errstate(divide="ignore", invalid="ignore"):
-            sx = np.where(dP[a, 0] > 0, (cx1 - P0[a, 0]) / dP[a, 0],
-                          np.where(dP[a, 0] < 0, (cx0 - P0[a, 0]) / dP[a, 0], np.inf))
-            sy = np.where(dP[a, 1] > 0, (cy1 - P0[a, 1]) / dP[a, 1],
-                          np.where(dP[a, 1] < 0, (cy0 - P0[a, 1]) / dP[a, 1], np.inf))
-        s_exit = np.minimum(np.minimum(sx, sy), s_max[a])
-        din = _ray_depth(d0[a], d1[a], s[a])
-        dout = _ray_depth(d0[a], d1[a], s_exit)
-        hi = np.maximum(din, dout)
-        lo = np.minimum(din, dout)
-        zc = _gather(pyramid, La, ix[a], iy[a])
-        skip = hi < zc
+        child = cell(a, La)
+        parent = cell(a, np.minimum(La + 1, top))
+        up = parent["skip"] & (La < top)
+        # the cell the ray moves across if it moves: the parent when it can
+        # be skipped, else the level-L cell
+        k = {key: np.where(up, parent[key], child[key]) for key in child}
+        skip = up | child["skip"]
         level0 = ~skip & (La == 0)
         descend = ~skip & (La > 0)
         own = level0 & (ix[a] == org_pix[a, 0]) & (iy[a] == org_pix[a, 1])
         test = level0 & ~own
         dq = depth[iy[a], ix[a]]
-        hit = test & (lo <= dq + thickness) & (armed[a] | (din < dq))
+        hit = test & (child["lo"] <= dq + thickness) & (armed[a] | (child["din"] < dq))
         advance = skip | own | (test & ~hit)
-        # the ray was in front of the depth buffer somewhere in a skipped cell
-        # or in a tested pixel it passes
-        armed[a[(skip & (s_exit > s[a])) | (test & (lo < dq))]] = True
-        # hits
+        # the ray was in front of the depth buffer somewhere in a cell it
+        # skipped for that reason, or in a tested pixel it passes
+        armed[a[(skip & k["front"] & (k["s_exit"] > s[a])) | (test & (child["lo"] < dq))]] = True
         ah = a[hit]
         codes[ah] = iy[ah] * W + ix[ah]
         active[ah] = False
-        # descents
-        L[a[descend]] -= 1
+        ad = a[descend]
+        L[ad] = np.maximum(L[ad] - 2, 0)
         # advances: leave at the segment end, else step into the next cell
-        ends = advance & (s_exit >= s_max[a])
+        se = k["s_exit"]
+        ends = advance & (se >= s_max[a])
         codes[a[ends]] = HIT_OFFSCREEN
         active[a[ends]] = False
         mv = advance & ~ends
         am = a[mv]
-        se = s_exit[mv]
-        crx = sx[mv] == se
-        cry = sy[mv] == se
-        px = P0[am, 0] + se * dP[am, 0]
-        py = P0[am, 1] + se * dP[am, 1]
-        nx = np.where(crx, np.where(dP[am, 0] > 0, cx1[mv], cx0[mv] - 1),
-                      np.clip(np.floor(px).astype(np.int64), cx0[mv], cx1[mv] - 1))
-        ny = np.where(cry, np.where(dP[am, 1] > 0, cy1[mv], cy0[mv] - 1),
-                      np.clip(np.floor(py).astype(np.int64), cy0[mv], cy1[mv] - 1))
+        sem = se[mv]
+        crx = k["sx"][mv] == sem
+        cry = k["sy"][mv] == sem
+        px = P0[am, 0] + sem * dP[am, 0]
+        py = P0[am, 1] + sem * dP[am, 1]
+        x0, x1, y0, y1 = k["x0"][mv], k["x1"][mv], k["y0"][mv], k["y1"][mv]
+        nx = np.where(crx, np.where(dP[am, 0] > 0, x1, x0 - 1),
+                      np.clip(np.floor(px).astype(np.int64), x0, x1 - 1))
+        ny = np.where(cry, np.where(dP[am, 1] > 0, y1, y0 - 1),
+                      np.clip(np.floor(py).astype(np.int64), y0, y1 - 1))
         ix[am] = nx
         iy[am] = ny
-        s[am] = se
-        L[am] = np.minimum(L[am] + 1, top)
+        s[am] = sem
+        L[am] = np.where(up[mv], np.minimum(L[am] + 1, top), L[am])
         # a step past the screen edge (boundary coinciding with it) leaves too
         gone = (nx < 0) | (nx >= W) | (ny < 0) | (ny >= H)
         codes[am[gone]] = HIT_OFFSCREEN

@@ -42,12 +42,18 @@ HIT_SKIPPED = -5
 
 
 def shade_pixels(cam, gbuf, env_rgb, params, pix, pyramid=None, mips=None,
-                 check_long_form=True):
+                 check_long_form=True, sensitivity=None):
     """Shade the flat pixel indices ``pix``.
 
     ``gbuf``: dict with ``depth`` [H][W], ``normal_rough``, ``albedo_metal``,
     ``radiance`` [H][W][4] (any float dtype; widened to float64).
     Returns dict(out [n][3], hits [n][S], steps [n][S]).
+
+    With ``sensitivity=eps`` (radians) the result also holds ``bound`` [n][3]:
+    how far each output can move when every direction the estimator looks up
+    (the normal of the diffuse lookup, each sample's ray direction) is off by
+    eps, to first order, with the hit pixels held fixed.  It is the
+    conditioning of the pixel, not part of the method.
     """
     c = camera.unpack(cam)
     W = c["W"]
@@ -62,7 +68,7 @@ def shade_pixels(cam, gbuf, env_rgb, params, pix, pyramid=None, mips=None,
     if mips is None:
         mips = env.build_mips(env_rgb)
     if pyramid is None and int(params["march"]) == 1:
-        pyramid = march.hiz_pyramid(depth)
+        pyramid = (march.hiz_pyramid(depth), march.hiz_max_pyramid(depth))
 
     i = pix % W
     j = pix // W
@@ -71,12 +77,20 @@ def shade_pixels(cam, gbuf, env_rgb, params, pix, pyramid=None, mips=None,
     hits = np.full((n, S), HIT_BACKGROUND, np.int64)
     steps = np.zeros((n, S), np.int64)
 
+    bound = np.zeros((n, 3))
+    res = dict(out=out, hits=hits, steps=steps)
+    if sensitivity is not None:
+        res["bound"] = bound
+
     bg = ~(D < np.inf)
     if bg.any():
-        out[bg] = env.bilinear(mips[0], camera.view_ray_dir(c, i[bg], j[bg]))
+        vd = camera.view_ray_dir(c, i[bg], j[bg])
+        out[bg] = env.bilinear(mips[0], vd)
+        if sensitivity is not None:
+            bound[bg] = _spread(lambda d: env.bilinear(mips[0], d), vd, sensitivity)
     fg = np.nonzero(~bg)[0]
     if fg.size == 0:
-        return dict(out=out, hits=hits, steps=steps)
+        return res
 
     # 1. per-pixel setup
     V0 = camera.pixel_view_point(c, i[fg], j[fg], D[fg])
@@ -91,11 +105,15 @@ def shade_pixels(cam, gbuf, env_rgb, params, pix, pyramid=None, mips=None,
     # 2. direct diffuse
     if not flags & NO_DIRECT:
         lam = env.roughness_level(mips, rho)
-        out[fg] += (1.0 - met)[:, None] * alb * env.trilinear(mips, nrm, lam)
+        kd = (1.0 - met)[:, None] * alb
+        out[fg] += kd * env.trilinear(mips, nrm, lam)
+        if sensitivity is not None:
+            bound[fg] += kd * _spread_components(lambda d: env.trilinear(mips, d, lam), nrm,
+                                                 sensitivity)
 
     if flags & NO_SPECULAR:
         hits[fg] = HIT_SKIPPED
-        return dict(out=out, hits=hits, steps=steps)
+        return res
 
     # 3. one ray per (pixel, sample)
     cos_no = brdf.dot(nrm, wo)
@@ -104,7 +122,7 @@ def shade_pixels(cam, gbuf, env_rgb, params, pix, pyramid=None, mips=None,
     pf = fg[front]                      # rows of the output that trace rays
     kf = np.nonzero(front)[0]           # rows of the per-pixel arrays above
     if pf.size == 0:
-        return dict(out=out, hits=hits, steps=steps)
+        return res
     rep = np.repeat(kf, S)
     sidx = np.tile(np.arange(S), kf.size)
     u1, u2 = philox.sample_uniforms(pix[np.repeat(pf, S)], sidx, params["frame"],
@@ -156,22 +174,81 @@ def shade_pixels(cam, gbuf, env_rgb, params, pix, pyramid=None, mips=None,
     out[pf] += contrib.sum(axis=1) / S
     hits[pf] = code.reshape(kf.size, S)
     steps[pf] = nit.reshape(kf.size, S)
-    return dict(out=out, hits=hits, steps=steps)
+
+    if sensitivity is not None and ok.any():
+        # each valid sample's contribution as a function of its direction,
+        # with its hit pixel (or miss) held fixed
+        f0o, woo, no, ao = f0[rep[ok]], wo_r[ok], n_r[ok], a_r[ok]
+        hit_o, code_o = hit[ok], code[ok]
+
+        def contribution(d):
+            hh = brdf.normalize(woo + d)
+            cnl = brdf.dot(no, d)
+            ww = brdf.weight_short(f0o, brdf.dot(woo, hh), np.maximum(cnl, 0.0), ao)
+            ww[cnl <= 0] = 0.0
+            LL = np.empty_like(ww)
+            LL[hit_o] = rad[code_o[hit_o], :3]
+            LL[~hit_o] = env.bilinear(mips[0], d[~hit_o])
+            return ww * LL
+
+        sp = np.zeros((rep.shape[0], 3))
+        sp[ok] = _spread(contribution, l[ok], sensitivity)
+        bound[pf] += sp.reshape(kf.size, S, 3).sum(axis=1) / S
+    return res
 
 
-def shade_frame(cam, gbuf, env_rgb, params, chunk=1 << 14):
-    """Shade every pixel; returns out [H][W][3], hits and steps [H][W][S]."""
+def _spread_components(fn, d, eps):
+    """Largest change of fn when one component of the unit vector d is scaled
+    by (1 +- eps) and d renormalised: the rounding of a stored, normalised
+    input, which leaves zero components zero (so a normal exactly at a pole
+    of the equirect map stays there)."""
+    d = brdf.normalize(d)
+    base = fn(d)
+    worst = np.zeros_like(base)
+    for k in range(3):
+        for sgn in (1.0, -1.0):
+            dd = d.copy()
+            dd[:, k] *= 1.0 + sgn * eps
+            worst = np.maximum(worst, np.abs(fn(brdf.normalize(dd)) - base))
+    return worst
+
+
+def _spread(fn, d, eps):
+    """Largest change of fn over the four directions d rotated by eps radians
+    towards two orthogonal tangents (fn maps [m][3] directions to [m][3])."""
+    d = brdf.normalize(d)
+    t, b = brdf.onb(d)
+    base = fn(d)
+    worst = np.zeros_like(base)
+    for tan in (t, b):
+        for sgn in (1.0, -1.0):
+            dd = np.cos(eps) * d + sgn * np.sin(eps) * tan
+            worst = np.maximum(worst, np.abs(fn(dd) - base))
+    return worst
+
+
+def shade_frame(cam, gbuf, env_rgb, params, chunk=1 << 14, sensitivity=None):
+    """Shade every pixel; returns out [H][W][3], hits and steps [H][W][S]
+    (and ``bound`` [H][W][3] with ``sensitivity``, see shade_pixels)."""
     W, H = int(cam["width"]), int(cam["height"])
     S = int(params["spp"])
     mips = env.build_mips(env_rgb)
-    pyramid = march.hiz_pyramid(gbuf["depth"]) if int(params["march"]) == 1 else None
+    pyramid = ((march.hiz_pyramid(gbuf["depth"]), march.hiz_max_pyramid(gbuf["depth"]))
+               if int(params["march"]) == 1 else None)
     out = np.zeros((H * W, 3))
+    bound = np.zeros((H * W, 3))
     hits = np.zeros((H * W, S), np.int64)
     steps = np.zeros((H * W, S), np.int64)
     per = max(1, chunk // max(S, 1))
     for k in range(0, H * W, per):
         pix = np.arange(k, min(k + per, H * W))
-        r = shade_pixels(cam, gbuf, env_rgb, params, pix, pyramid=pyramid, mips=mips)
+        r = shade_pixels(cam, gbuf, env_rgb, params, pix, pyramid=pyramid, mips=mips,
+                         sensitivity=sensitivity)
         out[pix], hits[pix], steps[pix] = r["out"], r["hits"], r["steps"]
-    return dict(out=out.reshape(H, W, 3), hits=hits.reshape(H, W, S),
-                steps=steps.reshape(H, W, S))
+        if sensitivity is not None:
+            bound[pix] = r["bound"]
+    res = dict(out=out.reshape(H, W, 3), hits=hits.reshape(H, W, S),
+               steps=steps.reshape(H, W, S))
+    if sensitivity is not None:
+        res["bound"] = bound.reshape(H, W, 3)
+    return res

@@ -10,9 +10,9 @@
 
 struct ssr_ctx {
     int device;
-    // workspace: min-depth pyramid (levels 1..top) and env mip chain
-    float* hiz;
-    int64_t hiz_cap;    // floats
+    // workspace: min-max depth pyramid and env mip chain
+    float2* hiz;
+    int64_t hiz_cap;    // float2 texels
     float4* mips;
     int64_t mips_cap;   // float4 texels
 };
@@ -136,15 +136,15 @@ int ssr_env_build_mips(const float* rgb, int32_t width, int32_t height, float* m
 int64_t ssr_hiz_floats(int32_t width, int32_t height) {
     ssr::HizLayout lay;
     if (!ssr::make_hiz_layout(width, height, &lay)) return 0;
-    return lay.total;
+    return 2 * lay.total;
 }
 
 int ssr_hiz_build(const float* depth, int32_t width, int32_t height, float* pyramid,
                   void* stream) {
     ssr::HizLayout lay;
-    if (!depth || !ssr::make_hiz_layout(width, height, &lay)) return SSR_E_ARG;
-    if (lay.total > 0 && !pyramid) return SSR_E_ARG;
-    return hip_status(ssr::launch_hiz(depth, lay, pyramid, static_cast<hipStream_t>(stream)));
+    if (!depth || !pyramid || !ssr::make_hiz_layout(width, height, &lay)) return SSR_E_ARG;
+    return hip_status(ssr::launch_hiz(depth, lay, reinterpret_cast<float2*>(pyramid),
+                                      static_cast<hipStream_t>(stream)));
 }
 
 int ssr_philox4x32_10(const uint32_t* ctr, const uint32_t* key, int64_t n, uint32_t* out,
@@ -183,8 +183,8 @@ int ssr_shade(ssr_ctx* ctx, const ssr_camera* cam, const ssr_gbuffer* g, const s
         if (st != SSR_OK) return st;
         mips = ctx->mips;
     }
-    const float* hiz = g->hiz;
-    if (p->march == SSR_MARCH_HIZ && hiz_lay.total > 0 && !hiz) {
+    const float2* hiz = reinterpret_cast<const float2*>(g->hiz);
+    if (p->march == SSR_MARCH_HIZ && !hiz) {
         st = ensure(&ctx->hiz, &ctx->hiz_cap, hiz_lay.total);
         if (st != SSR_OK) return st;
         st = hip_status(ssr::launch_hiz(g->depth, hiz_lay, ctx->hiz, s));

@@ -128,10 +128,11 @@ __device__ __forceinline__ float3 env_bilinear(const EnvLevel& lv, EnvAngles a) 
     if (x1 == lv.w) x1 = 0;
     const int y0 = min(max(cy.i0, 0), lv.h - 1);
     const int y1 = min(max(cy.i0 + 1, 0), lv.h - 1);
-    const float4 t00 = lv.texels[y0 * lv.w + x0];
-    const float4 t01 = lv.texels[y0 * lv.w + x1];
-    const float4 t10 = lv.texels[y1 * lv.w + x0];
-    const float4 t11 = lv.texels[y1 * lv.w + x1];
+    // RGB of the four taps (12 B loads from the 16 B texels)
+    const float3 t00 = *reinterpret_cast<const float3*>(lv.texels + y0 * lv.w + x0);
+    const float3 t01 = *reinterpret_cast<const float3*>(lv.texels + y0 * lv.w + x1);
+    const float3 t10 = *reinterpret_cast<const float3*>(lv.texels + y1 * lv.w + x0);
+    const float3 t11 = *reinterpret_cast<const float3*>(lv.texels + y1 * lv.w + x1);
     const float fx = cx.f, fy = cy.f;
     const float w00 = (1.0f - fx) * (1.0f - fy), w01 = fx * (1.0f - fy);
     const float w10 = (1.0f - fx) * fy, w11 = fx * fy;

@@ -21,13 +21,13 @@ struct EnvLayout {
     int64_t total;               // float4 texels
 };
 
-// Min-depth pyramid: level 0 is the caller's depth buffer; levels 1..top are
-// stored row-major, level after level, in one float buffer.
+// Min-max depth pyramid: levels 0..top, each texel a float2 (min, max) of the
+// depths it covers, row-major, level after level.
 struct HizLayout {
     int levels;               // top + 1
-    int w[kMaxLevels + 1], h[kMaxLevels + 1];
-    int64_t offset[kMaxLevels + 1];  // in floats; offset[0] unused
-    int64_t total;                   // floats for levels 1..top
+    int w[kMaxLevels], h[kMaxLevels];
+    int offset[kMaxLevels];   // in float2 texels
+    int64_t total;            // float2 texels
 };
 
 bool make_env_layout(int w, int h, EnvLayout* out);
@@ -45,7 +45,7 @@ struct ShadeArgs {
     const void* radiance;
     const float4* env;        // mip chain (EnvLayout)
     EnvLayout env_lay;
-    const float* hiz;         // levels 1..top (HizLayout)
+    const float2* hiz;        // min-max pyramid (HizLayout)
     HizLayout hiz_lay;
     int spp, max_steps, linear_samples;
     float step_len, max_dist, thickness;
@@ -57,7 +57,7 @@ struct ShadeArgs {
 
 hipError_t launch_env_mips(const float* rgb, const EnvLayout& lay, float4* mips,
                            hipStream_t stream);
-hipError_t launch_hiz(const float* depth, const HizLayout& lay, float* pyramid,
+hipError_t launch_hiz(const float* depth, const HizLayout& lay, float2* pyramid,
                       hipStream_t stream);
 hipError_t launch_shade(const ShadeArgs& args, int dtype, int march, hipStream_t stream);
 hipError_t launch_philox(const uint32_t* ctr, const uint32_t* key, int64_t n, uint32_t* out,

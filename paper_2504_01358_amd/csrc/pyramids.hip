@@ -1,8 +1,12 @@
 // Builders for the two pyramids the shading kernel reads:
 //  * the environment mip chain (Sec. 3.2, SampleEnvMap at level lambda):
 //    level k is the 2x2 box mean of level k-1;
-//  * the min-depth pyramid used by the hierarchical march: level L is the
-//    minimum of the (up to four) level L-1 children, ceil-halving to 1 x 1.
+//  * the depth pyramid used by the hierarchical march, kept in inverse depth:
+//    a level-0 texel is (1/D, 1/D) and a level-L texel holds the maximum and
+//    minimum inverse depth of its (up to four) level L-1 children (that is,
+//    one over the minimum and one over the maximum depth of the pixels it
+//    covers), ceil-halving to 1 x 1.  A background pixel (D = +inf) has
+//    inverse depth 0.
 #include "device_math.h"
 #include "kernels.h"
 
@@ -29,17 +33,15 @@ bool make_hiz_layout(int w, int h, HizLayout* out) {
     if (w < 1 || h < 1 || w > 16384 || h > 16384) return false;
     int lw = w, lh = h, L = 0;
     int64_t off = 0;
-    out->w[0] = w;
-    out->h[0] = h;
-    out->offset[0] = 0;
-    while (lw > 1 || lh > 1) {
+    for (;;) {
+        out->w[L] = lw;
+        out->h[L] = lh;
+        out->offset[L] = static_cast<int>(off);
+        off += static_cast<int64_t>(lw) * lh;
+        if (lw == 1 && lh == 1) break;
         lw = (lw + 1) / 2;
         lh = (lh + 1) / 2;
         ++L;
-        out->w[L] = lw;
-        out->h[L] = lh;
-        out->offset[L] = off;
-        off += static_cast<int64_t>(lw) * lh;
     }
     out->levels = L + 1;
     out->total = off;
@@ -81,13 +83,16 @@ hipError_t launch_env_mips(const float* rgb, const EnvLayout& lay, float4* mips,
 
 // ------------------------------------------------------------ Hi-Z pyramid --
 //
-// Pass 1: one 256-thread workgroup per 64 x 64 depth tile produces levels
-// 1..6 of that tile.  Each thread reduces a 4 x 4 pixel block to its two
-// level-1 rows and one level-2 texel in registers; the 16 x 16 level-2 texels
-// go through LDS for levels 3..6.  A texel at level L is the minimum of the
-// 2^L x 2^L pixel block it covers, clipped to the image (pixels outside count
-// as +inf), which equals the ceil-halving recursion.  Texels that do not
-// exist at their level (index >= W_L or H_L) are not written.
+// Pass 1: one 256-thread workgroup per 64 x 64 depth tile writes levels 0..6
+// of that tile.  Each thread reduces a 4 x 4 pixel block to its (1/D, 1/D)
+// level-0 pairs, two level-1 rows and one level-2 texel in registers; the
+// 16 x 16 level-2 texels go through LDS for levels 3..6.  A texel at level L
+// is the (max, min) inverse depth of the 2^L x 2^L pixel block it covers,
+// clipped to the image (pixels outside count as -inf for the max and +inf
+// for the min), which equals the ceil-halving recursion.  Texels that do not
+// exist at their level (index >= W_L or H_L) are not written.  1/D is the
+// correctly rounded quotient, and rounding is monotone, so a texel equals
+// the rounded inverse of the block's minimum and maximum depth exactly.
 //
 // Pass 2: the levels above 6.  When level 6 fits in LDS, one workgroup does
 // them all there; otherwise one launch per level from global memory.
@@ -95,31 +100,41 @@ hipError_t launch_env_mips(const float* rgb, const EnvLayout& lay, float4* mips,
 constexpr int kTile = 64;
 constexpr int kTileLevels = 6;
 
-__device__ __forceinline__ float depth_at(const float* __restrict__ d, int W, int H, int x, int y) {
-    return (x < W && y < H) ? d[static_cast<int64_t>(y) * W + x] : INFINITY;
+// (max inverse depth, min inverse depth) of two texels
+__device__ __forceinline__ float2 mm(float2 a, float2 b) {
+    return make_float2(fmaxf(a.x, b.x), fminf(a.y, b.y));
 }
 
 __global__ __launch_bounds__(256) void hiz_tile_kernel(const float* __restrict__ depth,
-                                                       float* __restrict__ pyr, HizLayout lay,
+                                                       float2* __restrict__ pyr, HizLayout lay,
                                                        int tile_levels) {
-    __shared__ float lds[2][16 * 16];
+    __shared__ float2 lds[2][16 * 16];
     const int W = lay.w[0], H = lay.h[0];
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
     const int x0 = blockIdx.x * kTile + tx * 4;
     const int y0 = blockIdx.y * kTile + ty * 4;
-    float p[4][4];
+    float2 p[4][4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+    for (int r = 0; r < 4; ++r) {
+        const int y = y0 + r;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) p[r][c] = depth_at(depth, W, H, x0 + c, y0 + r);
+        for (int c = 0; c < 4; ++c) {
+            const int x = x0 + c;
+            const bool in = x < W && y < H;
+            const float iz = in ? 1.0f / depth[static_cast<int64_t>(y) * W + x] : 0.0f;
+            p[r][c] = in ? make_float2(iz, iz) : make_float2(-INFINITY, INFINITY);
+            if (in) pyr[static_cast<int64_t>(y) * W + x] = p[r][c];
+        }
+    }
     // level 1: 2 x 2 texels per thread
-    float m1[2][2];
+    float2 m1[2][2];
 #pragma unroll
     for (int b = 0; b < 2; ++b)
 #pragma unroll
         for (int a = 0; a < 2; ++a)
-            m1[b][a] = fminf(fminf(p[2 * b][2 * a], p[2 * b][2 * a + 1]),
-                             fminf(p[2 * b + 1][2 * a], p[2 * b + 1][2 * a + 1]));
+            m1[b][a] = mm(mm(p[2 * b][2 * a], p[2 * b][2 * a + 1]),
+                          mm(p[2 * b + 1][2 * a], p[2 * b + 1][2 * a + 1]));
+    if (tile_levels < 1) return;
     {
         const int lx = x0 / 2, ly = y0 / 2;
 #pragma unroll
@@ -127,14 +142,13 @@ __global__ __launch_bounds__(256) void hiz_tile_kernel(const float* __restrict__
 #pragma unroll
             for (int a = 0; a < 2; ++a)
                 if (lx + a < lay.w[1] && ly + b < lay.h[1])
-                    pyr[lay.offset[1] + static_cast<int64_t>(ly + b) * lay.w[1] + lx + a] = m1[b][a];
+                    pyr[lay.offset[1] + (ly + b) * lay.w[1] + lx + a] = m1[b][a];
     }
     if (tile_levels < 2) return;
-    const float m2 = fminf(fminf(m1[0][0], m1[0][1]), fminf(m1[1][0], m1[1][1]));
+    const float2 m2 = mm(mm(m1[0][0], m1[0][1]), mm(m1[1][0], m1[1][1]));
     {
         const int lx = x0 / 4, ly = y0 / 4;
-        if (lx < lay.w[2] && ly < lay.h[2])
-            pyr[lay.offset[2] + static_cast<int64_t>(ly) * lay.w[2] + lx] = m2;
+        if (lx < lay.w[2] && ly < lay.h[2]) pyr[lay.offset[2] + ly * lay.w[2] + lx] = m2;
     }
     lds[0][ty * 16 + tx] = m2;
     int n = 16;  // current level's tile width in texels
@@ -144,68 +158,64 @@ __global__ __launch_bounds__(256) void hiz_tile_kernel(const float* __restrict__
         const int m = n / 2;
         if (static_cast<int>(threadIdx.x) < m * m) {
             const int a = threadIdx.x % m, b = threadIdx.x / m;
-            const float* s = lds[cur];
-            const float v = fminf(fminf(s[(2 * b) * n + 2 * a], s[(2 * b) * n + 2 * a + 1]),
-                                  fminf(s[(2 * b + 1) * n + 2 * a], s[(2 * b + 1) * n + 2 * a + 1]));
+            const float2* s = lds[cur];
+            const float2 v = mm(mm(s[(2 * b) * n + 2 * a], s[(2 * b) * n + 2 * a + 1]),
+                                mm(s[(2 * b + 1) * n + 2 * a], s[(2 * b + 1) * n + 2 * a + 1]));
             lds[cur ^ 1][b * m + a] = v;
             const int lx = blockIdx.x * (kTile >> L) + a, ly = blockIdx.y * (kTile >> L) + b;
-            if (lx < lay.w[L] && ly < lay.h[L])
-                pyr[lay.offset[L] + static_cast<int64_t>(ly) * lay.w[L] + lx] = v;
+            if (lx < lay.w[L] && ly < lay.h[L]) pyr[lay.offset[L] + ly * lay.w[L] + lx] = v;
         }
         cur ^= 1;
         n = m;
     }
 }
 
-// One level from the level below it (global memory), for any level >= 1.
-__global__ void hiz_level_kernel(const float* __restrict__ src, int sw, int sh,
-                                 float* __restrict__ dst, int dw, int dh) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= dw * dh) return;
-    const int x = i % dw, y = i / dw;
-    float v = src[(2 * y) * sw + 2 * x];
-    if (2 * x + 1 < sw) v = fminf(v, src[(2 * y) * sw + 2 * x + 1]);
+__device__ __forceinline__ float2 children(const float2* __restrict__ src, int sw, int sh, int x,
+                                           int y) {
+    float2 v = src[(2 * y) * sw + 2 * x];
+    if (2 * x + 1 < sw) v = mm(v, src[(2 * y) * sw + 2 * x + 1]);
     if (2 * y + 1 < sh) {
-        v = fminf(v, src[(2 * y + 1) * sw + 2 * x]);
-        if (2 * x + 1 < sw) v = fminf(v, src[(2 * y + 1) * sw + 2 * x + 1]);
+        v = mm(v, src[(2 * y + 1) * sw + 2 * x]);
+        if (2 * x + 1 < sw) v = mm(v, src[(2 * y + 1) * sw + 2 * x + 1]);
     }
-    dst[i] = v;
+    return v;
 }
 
-constexpr int kTopLdsFloats = 16384;  // 64 KB of LDS for the levels above the tile pass
+// One level from the level below it (global memory), for any level >= 1.
+__global__ void hiz_level_kernel(const float2* __restrict__ src, int sw, int sh,
+                                 float2* __restrict__ dst, int dw, int dh) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= dw * dh) return;
+    dst[i] = children(src, sw, sh, i % dw, i / dw);
+}
 
-// All levels above `first - 1` in one workgroup, ping-ponging through LDS.
-__global__ __launch_bounds__(1024) void hiz_top_kernel(float* __restrict__ pyr, HizLayout lay,
+constexpr int kTopLdsTexels = 8192;  // 64 KB of LDS for the levels above the tile pass
+
+// All levels from `first` up, in one workgroup, ping-ponging through LDS.
+__global__ __launch_bounds__(1024) void hiz_top_kernel(float2* __restrict__ pyr, HizLayout lay,
                                                        int first) {
-    extern __shared__ float lds[];
+    extern __shared__ float2 lds2[];
     const int sw0 = lay.w[first - 1], sh0 = lay.h[first - 1];
-    float* a = lds;
-    float* b = lds + sw0 * sh0;
+    float2* a = lds2;
+    float2* b = lds2 + sw0 * sh0;
     for (int i = threadIdx.x; i < sw0 * sh0; i += blockDim.x) a[i] = pyr[lay.offset[first - 1] + i];
     for (int L = first; L < lay.levels; ++L) {
         __syncthreads();
         const int sw = lay.w[L - 1], sh = lay.h[L - 1], dw = lay.w[L], dh = lay.h[L];
         for (int i = threadIdx.x; i < dw * dh; i += blockDim.x) {
-            const int x = i % dw, y = i / dw;
-            float v = a[(2 * y) * sw + 2 * x];
-            if (2 * x + 1 < sw) v = fminf(v, a[(2 * y) * sw + 2 * x + 1]);
-            if (2 * y + 1 < sh) {
-                v = fminf(v, a[(2 * y + 1) * sw + 2 * x]);
-                if (2 * x + 1 < sw) v = fminf(v, a[(2 * y + 1) * sw + 2 * x + 1]);
-            }
+            const float2 v = children(a, sw, sh, i % dw, i / dw);
             b[i] = v;
             pyr[lay.offset[L] + i] = v;
         }
-        float* t = a;
+        float2* t = a;
         a = b;
         b = t;
     }
 }
 
-hipError_t launch_hiz(const float* depth, const HizLayout& lay, float* pyramid,
+hipError_t launch_hiz(const float* depth, const HizLayout& lay, float2* pyramid,
                       hipStream_t stream) {
     const int top = lay.levels - 1;
-    if (top == 0) return hipSuccess;
     const int tile_levels = top < kTileLevels ? top : kTileLevels;
     const dim3 grid((lay.w[0] + kTile - 1) / kTile, (lay.h[0] + kTile - 1) / kTile);
     hipLaunchKernelGGL(hiz_tile_kernel, grid, dim3(256), 0, stream, depth, pyramid, lay,
@@ -214,8 +224,8 @@ hipError_t launch_hiz(const float* depth, const HizLayout& lay, float* pyramid,
         const int first = kTileLevels + 1;
         const int64_t need = static_cast<int64_t>(lay.w[first - 1]) * lay.h[first - 1] +
                              static_cast<int64_t>(lay.w[first]) * lay.h[first];
-        if (need <= kTopLdsFloats) {
-            hipLaunchKernelGGL(hiz_top_kernel, dim3(1), dim3(1024), need * sizeof(float), stream,
+        if (need <= kTopLdsTexels) {
+            hipLaunchKernelGGL(hiz_top_kernel, dim3(1), dim3(1024), need * sizeof(float2), stream,
                                pyramid, lay, first);
         } else {
             for (int L = first; L <= top; ++L) {

@@ -1,4 +1,4 @@
-// The shading kernel: one thread per pixel, all of that pixel's samples.
+// The shading kernels.
 //
 // Per pixel (Sec. 3.2 and Sec. 3.3):
 //   load the G-buffer, un-project the pixel centre, wo = toward the camera;
@@ -7,7 +7,7 @@
 //   half vector h; l = reflect(-wo, h); march l in screen space; radiance at
 //   the hit pixel (c1) or, if the ray left the screen or ran out of
 //   iterations, the environment at l; weight F(wo.h) G1(n.l);
-//   Kahan-accumulate weight * radiance;
+//   Kahan-accumulate weight * radiance in sample order;
 //   out = c_d + sum / S.
 //
 // The two marches implement the hit rule the library documents: a sample
@@ -62,7 +62,12 @@ __device__ __forceinline__ V3 view_to_world(const ShadeArgs& a, float X, float Y
               X * a.right[2] + Y * a.up[2] + Z * a.fwd[2]);
 }
 
-// ------------------------------------------------------------- marches --
+__device__ __forceinline__ V3 world_to_view(const ShadeArgs& a, V3 l) {
+    return v3(dot(l, v3(a.right[0], a.right[1], a.right[2])), dot(l, v3(a.up[0], a.up[1], a.up[2])),
+              dot(l, v3(a.fwd[0], a.fwd[1], a.fwd[2])));
+}
+
+// ---------------------------------------------------------- linear march --
 
 struct MarchResult {
     int code;
@@ -77,8 +82,9 @@ __device__ __forceinline__ MarchResult march_linear(const ShadeArgs& a, int i, i
         const float t = static_cast<float>(k) * a.step_len;
         const float X = V0.x + t * Dv.x, Y = V0.y + t * Dv.y, Z = V0.z + t * Dv.z;
         if (!(Z > a.z_near)) return MarchResult{SSR_HIT_OFFSCREEN, k};
-        const float px = a.cx + a.fx * X / Z;
-        const float py = a.cy - a.fy * Y / Z;
+        const float iz = 1.0f / Z;
+        const float px = a.cx + a.fx * X * iz;
+        const float py = a.cy - a.fy * Y * iz;
         if (!(px >= 0.0f && px < static_cast<float>(a.W) && py >= 0.0f &&
               py < static_cast<float>(a.H)))
             return MarchResult{SSR_HIT_OFFSCREEN, k};
@@ -92,238 +98,495 @@ __device__ __forceinline__ MarchResult march_linear(const ShadeArgs& a, int i, i
     return MarchResult{SSR_HIT_CAP, a.linear_samples};
 }
 
-// Exact first hit on the depth heightfield, hierarchical over the min
+// ------------------------------------------------------ hierarchical march --
+//
+// Exact first hit on the depth heightfield, hierarchical over the min-max
 // pyramid.  The ray is clipped at max_dist and the near plane and projected
-// to the screen segment P0 + s dP; its depth 1/(iz0 + s (iz1 - iz0)) is
-// monotone in s.  Each iteration skips the current level-L cell (ray in
-// front of the cell's minimum depth) and goes up a level, or goes down a
-// level, or tests one level-0 pixel.
-__device__ __forceinline__ MarchResult march_hiz(const ShadeArgs& a, int i, int j, V3 V0, V3 Dv) {
+// to the screen segment P0 + s dP.  Its inverse depth iz(s) = iz0 + s diz is
+// linear in s (perspective-correct interpolation), so the march runs in
+// inverse depth and needs no division: the pyramid holds (1/min D, 1/max D)
+// per cell.  A cell can be skipped when the ray's part inside it lies wholly
+// in front of the cell's nearest surface (its smallest inverse depth exceeds
+// 1/min D) or wholly behind the cell's farthest surface plus the thickness
+// (largest inverse depth b with b (1 + th/max D) < 1/max D).  Each iteration
+// looks at the level-L cell and its parent at once (two independent 8 B
+// gathers): skip the parent and go up a level, else skip the cell, else go
+// down two levels, else (level 0) test the pixel and step to the next one.
+//
+// The march is resumable (one iteration per call) so that a wave can keep
+// all its lanes busy with rays of different lengths.
+
+// Everything a ray needs for its march: the segment, computed when the ray is
+// drawn, and its extent, computed when a lane starts marching it.
+struct HizSegment {
+    bool valid;             // false: clipped away before it started (code -1, 0 iterations)
+    float dPx, dPy;         // P1 - P0 in pixels
+    float inv_dx, inv_dy;   // 1 / dP (+inf for a zero component)
+    float s_max;            // where the segment leaves the screen (at most 1)
+    float iz0, diz;         // inverse depth at s = 0 and its change over the segment
+};
+
+__device__ __forceinline__ HizSegment hiz_segment(const ShadeArgs& a, int i, int j, V3 V0, V3 Dv) {
+    HizSegment g;
     float t_end = a.max_dist;
     if (Dv.z < 0.0f) t_end = fminf(t_end, (a.z_near - V0.z) / Dv.z);
-    if (!(t_end > 0.0f)) return MarchResult{SSR_HIT_OFFSCREEN, 0};
+    g.valid = t_end > 0.0f;
     const float EX = V0.x + t_end * Dv.x, EY = V0.y + t_end * Dv.y, EZ = V0.z + t_end * Dv.z;
     const float P0x = static_cast<float>(i) + 0.5f, P0y = static_cast<float>(j) + 0.5f;
-    const float dPx = (a.cx + a.fx * EX / EZ) - P0x;
-    const float dPy = (a.cy - a.fy * EY / EZ) - P0y;
-    const float Wf = static_cast<float>(a.W), Hf = static_cast<float>(a.H);
-    float s_max = 1.0f;
-    if (dPx > 0.0f) s_max = fminf(s_max, (Wf - P0x) / dPx);
-    if (dPx < 0.0f) s_max = fminf(s_max, (0.0f - P0x) / dPx);
-    if (dPy > 0.0f) s_max = fminf(s_max, (Hf - P0y) / dPy);
-    if (dPy < 0.0f) s_max = fminf(s_max, (0.0f - P0y) / dPy);
-    const float iz0 = 1.0f / V0.z;
-    const float diz = 1.0f / EZ - iz0;
-    const int top = a.hiz_lay.levels - 1;
-
-    float s = 0.0f, d_in = V0.z;
-    int L = 0, ix = i, iy = j;
-    bool armed = false;
-    for (int it = 1; it <= a.max_steps; ++it) {
-        const int cx0 = (ix >> L) << L, cy0 = (iy >> L) << L;
-        const int cx1 = min(cx0 + (1 << L), a.W), cy1 = min(cy0 + (1 << L), a.H);
-        float sx = INFINITY, sy = INFINITY;
-        if (dPx > 0.0f) sx = (static_cast<float>(cx1) - P0x) / dPx;
-        if (dPx < 0.0f) sx = (static_cast<float>(cx0) - P0x) / dPx;
-        if (dPy > 0.0f) sy = (static_cast<float>(cy1) - P0y) / dPy;
-        if (dPy < 0.0f) sy = (static_cast<float>(cy0) - P0y) / dPy;
-        const float s_exit = fminf(fminf(sx, sy), s_max);
-        const float d_out = 1.0f / (iz0 + s_exit * diz);
-        const float hi = fmaxf(d_in, d_out), lo = fminf(d_in, d_out);
-        const float zc = (L == 0)
-                             ? a.depth[static_cast<int64_t>(iy) * a.W + ix]
-                             : a.hiz[a.hiz_lay.offset[L] +
-                                     static_cast<int64_t>(iy >> L) * a.hiz_lay.w[L] + (ix >> L)];
-        bool advance;
-        if (hi < zc) {
-            if (s_exit > s) armed = true;
-            advance = true;
-        } else if (L > 0) {
-            --L;
-            advance = false;
-        } else if (ix == i && iy == j) {
-            advance = true;
-        } else {
-            if (lo <= zc + a.thickness && (armed || d_in < zc))
-                return MarchResult{iy * a.W + ix, it};
-            if (lo < zc) armed = true;
-            advance = true;
-        }
-        if (advance) {
-            if (s_exit >= s_max) return MarchResult{SSR_HIT_OFFSCREEN, it};
-            int nx, ny;
-            if (sx == s_exit) {
-                nx = dPx > 0.0f ? cx1 : cx0 - 1;
-            } else {
-                const float px = P0x + s_exit * dPx;
-                nx = min(max(static_cast<int>(floorf(px)), cx0), cx1 - 1);
-            }
-            if (sy == s_exit) {
-                ny = dPy > 0.0f ? cy1 : cy0 - 1;
-            } else {
-                const float py = P0y + s_exit * dPy;
-                ny = min(max(static_cast<int>(floorf(py)), cy0), cy1 - 1);
-            }
-            if (nx < 0 || nx >= a.W || ny < 0 || ny >= a.H) return MarchResult{SSR_HIT_OFFSCREEN, it};
-            ix = nx;
-            iy = ny;
-            s = s_exit;
-            d_in = d_out;
-            L = min(L + 1, top);
-        }
-    }
-    return MarchResult{SSR_HIT_CAP, a.max_steps};
+    g.dPx = (a.cx + a.fx * EX / EZ) - P0x;
+    g.dPy = (a.cy - a.fy * EY / EZ) - P0y;
+    g.iz0 = 1.0f / V0.z;
+    g.diz = 1.0f / EZ - g.iz0;
+    return g;
 }
 
-// ------------------------------------------------------------- kernel --
+// The per-axis reciprocals and the screen exit of a segment.  A zero
+// component counts as travelling in the positive direction: its far boundary
+// is then never reached (s = +inf).
+__device__ __forceinline__ void hiz_extent(const ShadeArgs& a, int i, int j, HizSegment& g) {
+    const float P0x = static_cast<float>(i) + 0.5f, P0y = static_cast<float>(j) + 0.5f;
+    g.inv_dx = g.dPx != 0.0f ? 1.0f / g.dPx : INFINITY;
+    g.inv_dy = g.dPy != 0.0f ? 1.0f / g.dPy : INFINITY;
+    const float Wf = static_cast<float>(a.W), Hf = static_cast<float>(a.H);
+    g.s_max = fminf(fminf(((g.dPx >= 0.0f ? Wf : 0.0f) - P0x) * g.inv_dx,
+                          ((g.dPy >= 0.0f ? Hf : 0.0f) - P0y) * g.inv_dy),
+                    1.0f);
+}
 
+struct HizRay {
+    int i, j;             // origin pixel
+    float P0x, P0y;       // its centre
+    float bx, by;         // -P0 / dP: a boundary b is crossed at s = b / dP + bx
+    HizSegment g;
+    float s, iz_in;       // current point of the segment and the ray's inverse depth there
+    int L, ix, iy;        // level and the level-0 pixel containing the current point
+    bool armed;           // the ray has been in front of the depth buffer
+    int it;               // iterations so far
+};
+
+__device__ __forceinline__ void hiz_start(HizRay& r, int i, int j, const HizSegment& g) {
+    r.i = i;
+    r.j = j;
+    r.P0x = static_cast<float>(i) + 0.5f;
+    r.P0y = static_cast<float>(j) + 0.5f;
+    r.bx = -r.P0x * g.inv_dx;
+    r.by = -r.P0y * g.inv_dy;
+    r.g = g;
+    r.s = 0.0f;
+    r.iz_in = g.iz0;
+    r.L = 0;
+    r.ix = i;
+    r.iy = j;
+    r.armed = false;
+    r.it = 0;
+}
+
+// One iteration, branch-free.  Returns true when the ray is finished, with
+// its hit code.  `lvl[L]` holds (offset, width) of level L and of level
+// min(L + 1, top).
+__device__ __forceinline__ bool hiz_step(const ShadeArgs& a, const int4* lvl, HizRay& r, int& code) {
+    const int top = a.hiz_lay.levels - 1;
+    const int L = r.L, Lp = min(L + 1, top);
+    ++r.it;
+    const int4 lv = lvl[L];
+    // 32-bit byte offsets from a base held in SGPRs (the pyramid is < 4 GiB)
+    const char* base = reinterpret_cast<const char*>(a.hiz);
+    // (row index and width are below 2^14: the 24-bit multiply is exact)
+    const unsigned oc = (lv.x + __umul24(r.iy >> L, lv.y) + (r.ix >> L)) << 3;
+    const unsigned op = (lv.z + __umul24(r.iy >> Lp, lv.w) + (r.ix >> Lp)) << 3;
+    const float2 zc = *reinterpret_cast<const float2*>(base + oc);   // (1/min D, 1/max D)
+    const float2 zp = *reinterpret_cast<const float2*>(base + op);
+    const bool xpos = r.g.dPx >= 0.0f, ypos = r.g.dPy >= 0.0f;
+    // the level-L cell and its parent: bounds and where the segment leaves them
+    const int szc = 1 << L, szp = 1 << Lp;
+    const int cx0 = r.ix & -szc, cy0 = r.iy & -szc, px0 = r.ix & -szp, py0 = r.iy & -szp;
+    const int cx1 = min(cx0 + szc, a.W), cy1 = min(cy0 + szc, a.H);
+    const int px1 = min(px0 + szp, a.W), py1 = min(py0 + szp, a.H);
+    const float sxc = fmaf(static_cast<float>(xpos ? cx1 : cx0), r.g.inv_dx, r.bx);
+    const float syc = fmaf(static_cast<float>(ypos ? cy1 : cy0), r.g.inv_dy, r.by);
+    const float sxp = fmaf(static_cast<float>(xpos ? px1 : px0), r.g.inv_dx, r.bx);
+    const float syp = fmaf(static_cast<float>(ypos ? py1 : py0), r.g.inv_dy, r.by);
+    const float sec = fminf(fminf(sxc, syc), r.g.s_max), sep = fminf(fminf(sxp, syp), r.g.s_max);
+    const float izc = r.g.iz0 + sec * r.g.diz, izp = r.g.iz0 + sep * r.g.diz;
+    // far end (smaller inverse depth) and near end of the ray inside each cell
+    const float fc = fminf(r.iz_in, izc), nc = fmaxf(r.iz_in, izc);
+    const float fp = fminf(r.iz_in, izp), np = fmaxf(r.iz_in, izp);
+    const float th = a.thickness;
+    const bool front_c = fc > zc.x;
+    const bool skip_c = front_c | (nc * fmaf(th, zc.y, 1.0f) < zc.y);
+    const bool front_p = fp > zp.x;
+    const bool up = (L < top) & (front_p | (np * fmaf(th, zp.y, 1.0f) < zp.y));
+    // outcomes: skip the parent / skip the cell / go down / level-0 pixel
+    const bool stay = !up & !skip_c;
+    const bool at0 = L == 0;
+    const bool test = stay & at0 & ((r.ix != r.i) | (r.iy != r.j));
+    const bool hit = test & (r.armed | (r.iz_in > zc.x));
+    const bool move = !hit & (!stay | at0);
+    // the cell the segment moves across
+    const float se = up ? sep : sec;
+    const float sx = up ? sxp : sxc, sy = up ? syp : syc;
+    const int x0 = up ? px0 : cx0, x1 = up ? px1 : cx1, y0 = up ? py0 : cy0, y1 = up ? py1 : cy1;
+    r.armed = r.armed | (move & (up ? front_p : front_c) & !stay & (se > r.s)) | (test & (nc > zc.x));
+    // the pixel on the far side of the crossed boundary (both axes at a corner)
+    const int fx = min(max(static_cast<int>(floorf(fmaf(se, r.g.dPx, r.P0x))), x0), x1 - 1);
+    const int fy = min(max(static_cast<int>(floorf(fmaf(se, r.g.dPy, r.P0y))), y0), y1 - 1);
+    const int nx = sx == se ? (xpos ? x1 : x0 - 1) : fx;
+    const int ny = sy == se ? (ypos ? y1 : y0 - 1) : fy;
+    const bool leave = move & ((se >= r.g.s_max) | (nx < 0) | (nx >= a.W) | (ny < 0) | (ny >= a.H));
+    const bool step = move & !leave;
+    r.ix = step ? nx : r.ix;
+    r.iy = step ? ny : r.iy;
+    r.s = step ? se : r.s;
+    r.iz_in = step ? (up ? izp : izc) : r.iz_in;
+    r.L = (step & up) ? min(L + 1, top) : ((stay & !at0) ? max(L - 2, 0) : L);
+    code = hit ? r.iy * a.W + r.ix : (leave ? SSR_HIT_OFFSCREEN : SSR_HIT_CAP);
+    return hit | leave | (r.it >= a.max_steps);
+}
+
+// ------------------------------------------------------------ per pixel --
+
+struct Pixel {
+    bool bg;              // background (depth not finite)
+    float D, X0, Y0;      // view-space point of the pixel centre
+    V3 wo, n;             // toward the camera; shading normal
+    float rho, m;
+    V3 alb, f0;
+    float cos_no;
+    bool trace;           // specular samples are drawn
+    V3 t, b, ws;          // tangent frame; stretched view vector (visible normals)
+};
+
+template <int DT>
+__device__ __forceinline__ Pixel setup_pixel(const ShadeArgs& a, int i, int j, int64_t q) {
+    Pixel P;
+    P.D = a.depth[q];
+    P.bg = !(P.D < INFINITY);
+    const float D = P.bg ? 1.0f : P.D;
+    const float4 nr = Texel4<DT>::load(a.normal_rough, q);
+    const float4 am = Texel4<DT>::load(a.albedo_metal, q);
+    P.X0 = (static_cast<float>(i) + 0.5f - a.cx) * D / a.fx;
+    P.Y0 = -(static_cast<float>(j) + 0.5f - a.cy) * D / a.fy;
+    P.wo = -1.0f * normalize(view_to_world(a, P.X0, P.Y0, D));
+    P.n = normalize(v3(nr.x, nr.y, nr.z));
+    P.rho = fminf(fmaxf(nr.w, 0.0f), 1.0f);
+    P.m = fminf(fmaxf(am.w, 0.0f), 1.0f);
+    P.alb = v3(am.x, am.y, am.z);
+    P.f0 = v3(0.04f * (1.0f - P.m) + P.alb.x * P.m, 0.04f * (1.0f - P.m) + P.alb.y * P.m,
+              0.04f * (1.0f - P.m) + P.alb.z * P.m);
+    P.cos_no = dot(P.n, P.wo);
+    P.trace = !P.bg && !(a.flags & SSR_NO_SPECULAR) && P.cos_no > 0.0f;
+    onb(P.n, P.t, P.b);
+    const V3 wl = v3(dot(P.wo, P.t), dot(P.wo, P.b), P.cos_no);
+    // visible-normal sampling (Dupuy & Benyoub 2023): stretched view vector
+    P.ws = normalize(v3(P.rho * wl.x, P.rho * wl.y, wl.z));
+    return P;
+}
+
+// Direct diffuse c_d = (1 - m) a E_lambda(n), or the environment seen directly
+// for a background pixel.
+__device__ __forceinline__ float3 direct_term(const ShadeArgs& a, const Pixel& P, int i, int j) {
+    if (P.bg) {
+        const V3 d = normalize(view_to_world(a, (static_cast<float>(i) + 0.5f - a.cx) / a.fx,
+                                             -(static_cast<float>(j) + 0.5f - a.cy) / a.fy, 1.0f));
+        return env_bilinear(env_level(a, 0), env_angles(d));
+    }
+    if (a.flags & SSR_NO_DIRECT) return make_float3(0.0f, 0.0f, 0.0f);
+    const int top = a.env_lay.levels - 1;
+    // lambda = log2(1 + rho) * lambda_max, via log1p (no rounding of 1 + rho)
+    const float lam = fminf(fmaxf(log1pf(P.rho) * (static_cast<float>(top) * 1.44269504f), 0.0f),
+                            static_cast<float>(top));
+    const int k0 = static_cast<int>(floorf(lam));
+    const int k1 = min(k0 + 1, top);
+    const float t = lam - static_cast<float>(k0);
+    const EnvAngles ang = env_angles(P.n);
+    const float3 e0 = env_bilinear(env_level(a, k0), ang);
+    float3 e = e0;
+    if (t > 0.0f) {
+        const float3 e1 = env_bilinear(env_level(a, k1), ang);
+        e = make_float3((1.0f - t) * e0.x + t * e1.x, (1.0f - t) * e0.y + t * e1.y,
+                        (1.0f - t) * e0.z + t * e1.z);
+    }
+    const float k = 1.0f - P.m;
+    return make_float3(k * P.alb.x * e.x, k * P.alb.y * e.y, k * P.alb.z * e.z);
+}
+
+// ----------------------------------------------------------- per sample --
+
+struct SampleDir {
+    V3 l;         // reflected ray direction (world)
+    float cos_oh, cos_nl;
+};
+
+// Sample s of pixel q: Philox4x32-10 at counter (q, s, frame, 0) gives u1
+// (azimuth) and u2 (cap height) of a visible-normal sample h; l reflects wo
+// about h.
+__device__ __forceinline__ SampleDir sample_dir(const ShadeArgs& a, const Pixel& P, int64_t q,
+                                                int s) {
+    const uint4 x = philox4x32_10(
+        make_uint4(static_cast<uint32_t>(q), static_cast<uint32_t>(s), a.frame, 0u), a.key0, a.key1);
+    const float u1 = unit24(x.x), u2 = unit24(x.y);
+    // point on the spherical cap z > -ws.z: azimuth 2 pi u1, height from u2.
+    // h_std.z = z + ws.z = (1 - u2)(1 + ws.z) and 1 - z^2 = (1 - z)(1 + z) with
+    // 1 - z = u2 (1 + ws.z), 1 + z = (1 - u2)(1 + ws.z) + (1 - ws.z): no cancellation.
+    float sphi, cphi;
+    sincospif(2.0f * u1, &sphi, &cphi);
+    const float one_m_u2 = 1.0f - u2;
+    const float opz = 1.0f + P.ws.z;
+    const float hz = one_m_u2 * opz;
+    const float sin2 = (u2 * opz) * (hz + (1.0f - P.ws.z));
+    const float st = sqrtf(fmaxf(sin2, 0.0f));
+    const V3 hl = normalize(v3(P.rho * (st * cphi + P.ws.x), P.rho * (st * sphi + P.ws.y), hz));
+    const V3 h = v3(hl.x * P.t.x + hl.y * P.b.x + hl.z * P.n.x,
+                    hl.x * P.t.y + hl.y * P.b.y + hl.z * P.n.y,
+                    hl.x * P.t.z + hl.y * P.b.z + hl.z * P.n.z);
+    SampleDir d;
+    d.cos_oh = dot(P.wo, h);
+    d.l = (2.0f * d.cos_oh) * h - P.wo;
+    d.cos_nl = dot(P.n, d.l);
+    return d;
+}
+
+// Weight F(wo.h) G1(n.l) times the radiance found (c1 at a hit pixel, the
+// unfiltered environment otherwise), Kahan-accumulated per channel.
+template <int DT>
+__device__ __forceinline__ void accumulate(const ShadeArgs& a, const Pixel& P, const SampleDir& d,
+                                           int code, float* sum, float* cmp) {
+    float3 Lr;
+    if (code >= 0) {
+        const float4 c1 = Texel4<DT>::load(a.radiance, code);
+        Lr = make_float3(c1.x, c1.y, c1.z);
+    } else {
+        Lr = env_bilinear(env_level(a, 0), env_angles(d.l));
+    }
+    const float fc = 1.0f - d.cos_oh;
+    const float fc2 = fc * fc;
+    const float fr = fc2 * fc2 * fc;
+    const float g1 = smith_g1(fmaxf(d.cos_nl, 0.0f), P.rho * P.rho);
+    kahan_add(sum[0], cmp[0], (P.f0.x + (1.0f - P.f0.x) * fr) * g1 * Lr.x);
+    kahan_add(sum[1], cmp[1], (P.f0.y + (1.0f - P.f0.y) * fr) * g1 * Lr.y);
+    kahan_add(sum[2], cmp[2], (P.f0.z + (1.0f - P.f0.z) * fr) * g1 * Lr.z);
+}
+
+__device__ __forceinline__ int fill_code(const ShadeArgs& a, const Pixel& P) {
+    return P.bg ? SSR_HIT_BACKGROUND
+                : ((a.flags & SSR_NO_SPECULAR) ? SSR_HIT_SKIPPED : SSR_HIT_INVALID);
+}
+
+__device__ __forceinline__ void write_out(const ShadeArgs& a, int64_t q, float3 cd, const float* sum) {
+    const float invS = 1.0f / static_cast<float>(a.spp);
+    a.out[3 * q + 0] = cd.x + sum[0] * invS;
+    a.out[3 * q + 1] = cd.y + sum[1] * invS;
+    a.out[3 * q + 2] = cd.z + sum[2] * invS;
+}
+
+// -------------------------------------------------- linear-march kernel --
+//
 // Workgroups of 256 threads shade 16 x 16 pixel tiles; each wave64 takes an
-// 8 x 8 quadrant so that its rays start close together on the screen.
-template <int DT, int MARCH>
-__global__ __launch_bounds__(256) void shade_kernel(const ShadeArgs a) {
+// 8 x 8 quadrant; each thread shades one pixel, its samples in order.
+template <int DT>
+__global__ __launch_bounds__(256) void shade_linear_kernel(const ShadeArgs a) {
+    const int tiles_x = (a.W + 15) / 16;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int i = blockIdx.x * 16 + (wave & 1) * 8 + (lane & 7);
-    const int j = blockIdx.y * 16 + (wave >> 1) * 8 + (lane >> 3);
+    const int i = (blockIdx.x % tiles_x) * 16 + (wave & 1) * 8 + (lane & 7);
+    const int j = (blockIdx.x / tiles_x) * 16 + (wave >> 1) * 8 + (lane >> 3);
     if (i >= a.W || j >= a.H) return;
     const int64_t q = static_cast<int64_t>(j) * a.W + i;
     const int S = a.spp;
-    const float D = a.depth[q];
-
-    if (!(D < INFINITY)) {
-        // background: the environment seen directly
-        const V3 d = normalize(view_to_world(a, (static_cast<float>(i) + 0.5f - a.cx) / a.fx,
-                                             -(static_cast<float>(j) + 0.5f - a.cy) / a.fy, 1.0f));
-        const float3 e = env_bilinear(env_level(a, 0), env_angles(d));
-        a.out[3 * q + 0] = e.x;
-        a.out[3 * q + 1] = e.y;
-        a.out[3 * q + 2] = e.z;
-        for (int s = 0; s < S; ++s) {
-            if (a.hits) a.hits[q * S + s] = SSR_HIT_BACKGROUND;
-            if (a.steps) a.steps[q * S + s] = 0;
-        }
-        return;
-    }
-
-    const float4 nr = Texel4<DT>::load(a.normal_rough, q);
-    const float4 am = Texel4<DT>::load(a.albedo_metal, q);
-    const float X0 = (static_cast<float>(i) + 0.5f - a.cx) * D / a.fx;
-    const float Y0 = -(static_cast<float>(j) + 0.5f - a.cy) * D / a.fy;
-    const V3 wo = -1.0f * normalize(view_to_world(a, X0, Y0, D));
-    const V3 n = normalize(v3(nr.x, nr.y, nr.z));
-    const float rho = fminf(fmaxf(nr.w, 0.0f), 1.0f);
-    const float m = fminf(fmaxf(am.w, 0.0f), 1.0f);
-    const V3 alb = v3(am.x, am.y, am.z);
-    const V3 f0 = v3(0.04f * (1.0f - m) + alb.x * m, 0.04f * (1.0f - m) + alb.y * m,
-                     0.04f * (1.0f - m) + alb.z * m);
-
-    float3 cd = make_float3(0.0f, 0.0f, 0.0f);
-    if (!(a.flags & SSR_NO_DIRECT)) {
-        const int top = a.env_lay.levels - 1;
-        const float lam = fminf(fmaxf(log2f(rho + 1.0f) * static_cast<float>(top), 0.0f),
-                                static_cast<float>(top));
-        const int k0 = static_cast<int>(floorf(lam));
-        const int k1 = min(k0 + 1, top);
-        const float t = lam - static_cast<float>(k0);
-        const EnvAngles ang = env_angles(n);
-        const float3 e0 = env_bilinear(env_level(a, k0), ang);
-        float3 e = e0;
-        if (t > 0.0f) {
-            const float3 e1 = env_bilinear(env_level(a, k1), ang);
-            e = make_float3((1.0f - t) * e0.x + t * e1.x, (1.0f - t) * e0.y + t * e1.y,
-                            (1.0f - t) * e0.z + t * e1.z);
-        }
-        cd = make_float3((1.0f - m) * alb.x * e.x, (1.0f - m) * alb.y * e.y,
-                         (1.0f - m) * alb.z * e.z);
-    }
-
-    float sum_r = 0.0f, sum_g = 0.0f, sum_b = 0.0f;
-    float cmp_r = 0.0f, cmp_g = 0.0f, cmp_b = 0.0f;
-    const float cos_no = dot(n, wo);
-    const bool trace = !(a.flags & SSR_NO_SPECULAR) && cos_no > 0.0f;
-    const int fill = (a.flags & SSR_NO_SPECULAR) ? SSR_HIT_SKIPPED : SSR_HIT_INVALID;
-    if (trace) {
-        V3 t, b;
-        onb(n, t, b);
-        const V3 wl = v3(dot(wo, t), dot(wo, b), cos_no);
-        // visible-normal sampling (Dupuy & Benyoub 2023): stretched view vector
-        const V3 ws = normalize(v3(rho * wl.x, rho * wl.y, wl.z));
-        const float a2 = rho * rho;
-        const V3 V0 = v3(X0, Y0, D);
-        for (int s = 0; s < S; ++s) {
-            const uint4 x = philox4x32_10(
-                make_uint4(static_cast<uint32_t>(q), static_cast<uint32_t>(s), a.frame, 0u), a.key0,
-                a.key1);
-            const float u1 = unit24(x.x), u2 = unit24(x.y);
-            // point on the spherical cap z > -ws.z: azimuth 2 pi u1, height from u2.
-            // h_std.z = z + ws.z = (1 - u2)(1 + ws.z) and 1 - z^2 = (1 - z)(1 + z) with
-            // 1 - z = u2 (1 + ws.z), 1 + z = (1 - u2)(1 + ws.z) + (1 - ws.z): no cancellation.
-            float sphi, cphi;
-            sincospif(2.0f * u1, &sphi, &cphi);
-            const float one_m_u2 = 1.0f - u2;
-            const float opz = 1.0f + ws.z;
-            const float hz = one_m_u2 * opz;
-            const float sin2 = (u2 * opz) * (hz + (1.0f - ws.z));
-            const float st = sqrtf(fmaxf(sin2, 0.0f));
-            const V3 hl = normalize(v3(rho * (st * cphi + ws.x), rho * (st * sphi + ws.y), hz));
-            const V3 h = v3(hl.x * t.x + hl.y * b.x + hl.z * n.x, hl.x * t.y + hl.y * b.y + hl.z * n.y,
-                            hl.x * t.z + hl.y * b.z + hl.z * n.z);
-            const float cos_oh = dot(wo, h);
-            const V3 l = (2.0f * cos_oh) * h - wo;
-            const float cos_nl = dot(n, l);
-            int code = SSR_HIT_INVALID, iters = 0;
-            if (cos_nl > 0.0f) {
-                const V3 Dv = v3(dot(l, v3(a.right[0], a.right[1], a.right[2])),
-                                 dot(l, v3(a.up[0], a.up[1], a.up[2])),
-                                 dot(l, v3(a.fwd[0], a.fwd[1], a.fwd[2])));
-                const MarchResult r = MARCH == 0 ? march_linear(a, i, j, V0, Dv)
-                                                 : march_hiz(a, i, j, V0, Dv);
+    const Pixel P = setup_pixel<DT>(a, i, j, q);
+    const int fill = fill_code(a, P);
+    float sum[3] = {0.0f, 0.0f, 0.0f}, cmp[3] = {0.0f, 0.0f, 0.0f};
+    for (int s = 0; s < S; ++s) {
+        int code = fill, iters = 0;
+        if (P.trace) {
+            const SampleDir d = sample_dir(a, P, q, s);
+            if (d.cos_nl > 0.0f) {
+                const MarchResult r = march_linear(a, i, j, v3(P.X0, P.Y0, P.D), world_to_view(a, d.l));
                 code = r.code;
                 iters = r.iters;
-                float3 Lr;
-                if (code >= 0) {
-                    const float4 c1 = Texel4<DT>::load(a.radiance, code);
-                    Lr = make_float3(c1.x, c1.y, c1.z);
-                } else {
-                    Lr = env_bilinear(env_level(a, 0), env_angles(l));
-                }
-                const float fc = 1.0f - cos_oh;
-                const float fc2 = fc * fc;
-                const float fr = fc2 * fc2 * fc;
-                const float g1 = smith_g1(cos_nl, a2);
-                kahan_add(sum_r, cmp_r, (f0.x + (1.0f - f0.x) * fr) * g1 * Lr.x);
-                kahan_add(sum_g, cmp_g, (f0.y + (1.0f - f0.y) * fr) * g1 * Lr.y);
-                kahan_add(sum_b, cmp_b, (f0.z + (1.0f - f0.z) * fr) * g1 * Lr.z);
+                accumulate<DT>(a, P, d, code, sum, cmp);
             }
-            if (a.hits) a.hits[q * S + s] = code;
-            if (a.steps) a.steps[q * S + s] = iters;
         }
-    } else {
-        for (int s = 0; s < S; ++s) {
-            if (a.hits) a.hits[q * S + s] = fill;
-            if (a.steps) a.steps[q * S + s] = 0;
+        if (a.hits) a.hits[q * S + s] = code;
+        if (a.steps) a.steps[q * S + s] = iters;
+    }
+    write_out(a, q, direct_term(a, P, i, j), sum);
+}
+
+// ------------------------------------------------ hierarchical-march kernel --
+//
+// One wave64 per 8 x 8 pixel tile, samples in chunks of kChunk per pixel.
+// For each chunk:
+//   1. generate: each lane draws its pixel's samples of the chunk; the rays
+//      that need marching go to an LDS queue, compacted (ballot + popcount);
+//      the others get their hit code at once;
+//   2. march: the lanes take rays from the queue, any lane any ray, and a
+//      lane that finishes takes the next one.  Idle lanes are refilled
+//      together once kRefillMin of them wait (or the queue is shorter), so
+//      the wave pays for the average ray length instead of the longest ray
+//      of every sample;
+//   3. finish: each lane draws its samples again, reads their hit codes and
+//      accumulates weight x radiance in sample order (Kahan), so the result
+//      does not depend on which lane marched which ray.
+#ifndef SSR_CHUNK
+#define SSR_CHUNK 4
+#endif
+#ifndef SSR_REFILL_MIN
+#define SSR_REFILL_MIN 8
+#endif
+#ifndef SSR_WAVES_PER_EU
+#define SSR_WAVES_PER_EU 5
+#endif
+constexpr int kChunk = SSR_CHUNK;
+constexpr int kRefillMin = SSR_REFILL_MIN;
+
+template <int DT>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(SSR_WAVES_PER_EU, 8)))
+void shade_hiz_kernel(const ShadeArgs a) {
+    __shared__ int4 lvl[kMaxLevels];
+    __shared__ float4 q_seg[kChunk * 64];   // queued rays: (dPx, dPy, iz0, diz)
+    __shared__ int q_slot[kChunk * 64];     //   and their slot k * 64 + lane
+    __shared__ int r_code[kChunk * 64];     // per (sample of the chunk, lane)
+    __shared__ int r_iters[kChunk * 64];
+    const int lane = threadIdx.x;
+    {
+        const int nl = a.hiz_lay.levels;
+        if (lane < nl) {
+            const int Lp = min(lane + 1, nl - 1);
+            lvl[lane] = make_int4(a.hiz_lay.offset[lane], a.hiz_lay.w[lane], a.hiz_lay.offset[Lp],
+                                  a.hiz_lay.w[Lp]);
         }
     }
-    const float invS = 1.0f / static_cast<float>(S);
-    a.out[3 * q + 0] = cd.x + sum_r * invS;
-    a.out[3 * q + 1] = cd.y + sum_g * invS;
-    a.out[3 * q + 2] = cd.z + sum_b * invS;
+    const int tiles_x = (a.W + 7) / 8;
+    const int ti = (blockIdx.x % tiles_x) * 8, tj = (blockIdx.x / tiles_x) * 8;
+    const int i = ti + (lane & 7), j = tj + (lane >> 3);
+    const bool inb = i < a.W && j < a.H;
+    const int64_t q = inb ? static_cast<int64_t>(j) * a.W + i : 0;
+    const int S = a.spp;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    float sum[3] = {0.0f, 0.0f, 0.0f}, cmp[3] = {0.0f, 0.0f, 0.0f};
+    __syncthreads();
+
+    for (int s0 = 0; s0 < S; s0 += kChunk) {
+        const int nch = min(kChunk, S - s0);
+        // 1. generate.  The per-pixel setup is recomputed in each phase rather
+        // than kept live through the march (the compiler barrier stops it
+        // being hoisted out of the chunk loop).
+        int qn = 0;
+        {
+            asm volatile("" ::: "memory");
+            const Pixel P = setup_pixel<DT>(a, i, j, q);
+            const bool trace = inb && P.trace;
+            const int fill = fill_code(a, P);
+#pragma unroll 1
+            for (int k = 0; k < nch; ++k) {
+                int code = fill;
+                bool queue = false;
+                HizSegment g;
+                if (trace) {
+                    const SampleDir d = sample_dir(a, P, q, s0 + k);
+                    if (d.cos_nl > 0.0f) {
+                        g = hiz_segment(a, i, j, v3(P.X0, P.Y0, P.D), world_to_view(a, d.l));
+                        queue = g.valid;
+                        code = SSR_HIT_OFFSCREEN;
+                    }
+                }
+                const unsigned long long m = __ballot(queue);
+                if (queue) {
+                    const int pos = qn + __popcll(m & below);
+                    q_seg[pos] = make_float4(g.dPx, g.dPy, g.iz0, g.diz);
+                    q_slot[pos] = k * 64 + lane;
+                } else {
+                    r_code[k * 64 + lane] = code;
+                    r_iters[k * 64 + lane] = 0;
+                }
+                qn += __popcll(m);
+            }
+        }
+        __syncthreads();
+        // 2. march the queue
+        {
+            HizRay r;
+            int slot = 0;
+            bool active = false;
+            int qh = 0;
+            for (;;) {
+                const unsigned long long idle = __ballot(!active);
+                const int nidle = __popcll(idle);
+                const int rem = qn - qh;
+                if (rem > 0 && nidle >= min(kRefillMin, rem)) {
+                    const int rank = __popcll(idle & below);
+                    if (!active && rank < rem) {
+                        const float4 gq = q_seg[qh + rank];
+                        slot = q_slot[qh + rank];
+                        const int ln = slot & 63;
+                        const int ri = ti + (ln & 7), rj = tj + (ln >> 3);
+                        HizSegment g;
+                        g.valid = true;
+                        g.dPx = gq.x;
+                        g.dPy = gq.y;
+                        g.iz0 = gq.z;
+                        g.diz = gq.w;
+                        hiz_extent(a, ri, rj, g);
+                        hiz_start(r, ri, rj, g);
+                        active = true;
+                    }
+                    qh += min(nidle, rem);
+                }
+                if (!__any(active)) break;
+                if (active) {
+                    int code;
+                    if (hiz_step(a, lvl, r, code)) {
+                        r_code[slot] = code;
+                        r_iters[slot] = r.it;
+                        active = false;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        // 3. finish
+        {
+            asm volatile("" ::: "memory");
+            const Pixel P = setup_pixel<DT>(a, i, j, q);
+#pragma unroll 1
+            for (int k = 0; k < nch; ++k) {
+                const int code = r_code[k * 64 + lane];
+                if (inb && P.trace &&
+                    (code >= 0 || code == SSR_HIT_OFFSCREEN || code == SSR_HIT_CAP)) {
+                    const SampleDir d = sample_dir(a, P, q, s0 + k);
+                    accumulate<DT>(a, P, d, code, sum, cmp);
+                }
+                if (inb) {
+                    if (a.hits) a.hits[q * S + s0 + k] = code;
+                    if (a.steps) a.steps[q * S + s0 + k] = r_iters[k * 64 + lane];
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (!inb) return;
+    const Pixel P = setup_pixel<DT>(a, i, j, q);
+    write_out(a, q, direct_term(a, P, i, j), sum);
 }
 
 hipError_t launch_shade(const ShadeArgs& args, int dtype, int march, hipStream_t stream) {
-    const dim3 grid((args.W + 15) / 16, (args.H + 15) / 16);
-    const dim3 block(256);
-#define SSR_LAUNCH(DT, MR) \
-    hipLaunchKernelGGL((shade_kernel<DT, MR>), grid, block, 0, stream, args)
     if (march == 0) {
-        if (dtype == 0) SSR_LAUNCH(0, 0);
-        else if (dtype == 1) SSR_LAUNCH(1, 0);
-        else SSR_LAUNCH(2, 0);
-    } else {
-        if (dtype == 0) SSR_LAUNCH(0, 1);
-        else if (dtype == 1) SSR_LAUNCH(1, 1);
-        else SSR_LAUNCH(2, 1);
-    }
+        const dim3 grid(((args.W + 15) / 16) * ((args.H + 15) / 16));
+#define SSR_LAUNCH(DT) \
+    hipLaunchKernelGGL((shade_linear_kernel<DT>), grid, dim3(256), 0, stream, args)
+        if (dtype == 0) SSR_LAUNCH(0);
+        else if (dtype == 1) SSR_LAUNCH(1);
+        else SSR_LAUNCH(2);
 #undef SSR_LAUNCH
+    } else {
+        const dim3 grid(((args.W + 7) / 8) * ((args.H + 7) / 8));
+#define SSR_LAUNCH(DT) \
+    hipLaunchKernelGGL((shade_hiz_kernel<DT>), grid, dim3(64), 0, stream, args)
+        if (dtype == 0) SSR_LAUNCH(0);
+        else if (dtype == 1) SSR_LAUNCH(1);
+        else SSR_LAUNCH(2);
+#undef SSR_LAUNCH
+    }
     return hipGetLastError();
 }
 

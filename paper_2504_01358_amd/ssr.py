@@ -196,8 +196,7 @@ class Context:
             if hiz.numel() != hiz_floats(W, H):
                 raise ValueError("hiz has the wrong size for this depth buffer")
         g = GBuffer(depth.data_ptr(), normal_rough.data_ptr(), albedo_metal.data_ptr(),
-                    radiance.data_ptr(), _GBUF_DTYPES[dt],
-                    None if hiz is None or hiz.numel() == 0 else hiz.data_ptr())
+                    radiance.data_ptr(), _GBUF_DTYPES[dt], None if hiz is None else hiz.data_ptr())
         e = Env(env.data_ptr(), int(env.shape[1]), int(env.shape[0]),
                 None if env_mips is None else env_mips.data_ptr())
         st = lib.ssr_shade(self._h, ctypes.byref(cam), ctypes.byref(g), ctypes.byref(e),
@@ -229,15 +228,18 @@ def hiz_floats(width, height) -> int:
 
 
 def hiz_build(depth, out=None, stream=None):
-    """Levels 1..top of the min-depth pyramid of ``depth`` [H][W] (flat float32)."""
+    """Min-max pyramid (levels 0..top, (min, max) float pairs) of ``depth`` [H][W]."""
     _dev_tensor(depth, "depth", torch.float32)
     H, W = depth.shape
     n = hiz_floats(W, H)
+    if n == 0:
+        raise SSRError(-1, "hiz_build: depth must be 1..16384 on each side")
     if out is None:
-        out = torch.empty(max(n, 1), dtype=torch.float32, device=depth.device)
+        out = torch.empty(n, dtype=torch.float32, device=depth.device)
+    _dev_tensor(out, "out", torch.float32, (n,))
     _check(lib.ssr_hiz_build(_ptr(depth), W, H, _ptr(out), _stream(stream, depth.device)),
            "ssr_hiz_build")
-    return out[:n]
+    return out
 
 
 def philox4x32_10(ctr, key, out=None, stream=None):

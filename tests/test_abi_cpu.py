@@ -80,13 +80,13 @@ def test_sizes_and_status_strings(lib):
     assert lib.env_mips_floats(2, 1) == 8
     for bad in ((512, 255), (500, 250), (256, 256), (0, 0), (2 * 16384, 16384)):
         assert lib.env_mips_floats(*bad) == 0
-    # min pyramid, levels 1..top with ceil halving
+    # min-max pyramid, levels 0..top with ceil halving, two floats per texel
     def hiz(w, h):
-        n = 0
+        n = w * h
         while w > 1 or h > 1:
             w, h = (w + 1) // 2, (h + 1) // 2
             n += w * h
-        return n
+        return 2 * n
     for w, h in ((1920, 1080), (1, 1), (7, 3), (3840, 2160), (16384, 1)):
         assert lib.hiz_floats(w, h) == hiz(w, h)
     assert lib.hiz_floats(0, 5) == 0 and lib.hiz_floats(16385, 2) == 0

@@ -240,18 +240,20 @@ def test_env_mips_are_block_means():
 # --------------------------------------------------------------- pyramid ---
 
 @pytest.mark.parametrize("h,w", [(1, 1), (1, 7), (5, 3), (9, 13), (16, 16), (33, 17)])
-def test_hiz_pyramid_is_block_min(h, w):
+def test_hiz_pyramids_are_block_min_max(h, w):
     rng = np.random.default_rng(h * 100 + w)
     d = rng.uniform(1, 10, (h, w))
     d[rng.uniform(size=(h, w)) < 0.2] = np.inf
     lv = march.hiz_pyramid(d)
-    assert lv[-1].shape == (1, 1)
-    for L, img in enumerate(lv):
+    lx = march.hiz_max_pyramid(d)
+    assert lv[-1].shape == (1, 1) and len(lx) == len(lv)
+    for L, (img, imx) in enumerate(zip(lv, lx)):
         b = 2 ** L
-        assert img.shape == (-(-h // b), -(-w // b))
+        assert img.shape == (-(-h // b), -(-w // b)) == imx.shape
         for y in range(img.shape[0]):
             for x in range(img.shape[1]):
                 assert img[y, x] == d[y * b:(y + 1) * b, x * b:(x + 1) * b].min()
+                assert imx[y, x] == d[y * b:(y + 1) * b, x * b:(x + 1) * b].max()
 
 
 # ----------------------------------------------------------------- march ---
@@ -289,7 +291,7 @@ def test_hiz_march_equals_brute_force(h, w):
             jj, ii = np.meshgrid(np.arange(h), np.arange(w), indexing="ij")
             depth = 1.5 + 0.08 * jj + 0.03 * ii
         org, V0, Dv = _random_rays(rng, cam, depth, 150)
-        pyr = march.hiz_pyramid(depth)
+        pyr = (march.hiz_pyramid(depth), march.hiz_max_pyramid(depth))
         for thick in (0.05, 0.5):
             want = march.brute_force_first_hit(cam, depth, org, V0, Dv, 6.0, thick)
             got, it = march.march_hiz(cam, pyr, org, V0, Dv, 10 ** 6, 6.0, thick)
