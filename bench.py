@@ -1,7 +1,7 @@
 """Throughput of screen-space GGX shading on one MI355X.
 
 One step = one frame of the whole hot path on the headline workload: build
-the min-depth pyramid of the frame's depth buffer, then shade every pixel
+the (min, max) inverse-depth pyramid of the frame's depth buffer, then shade every pixel
 (direct diffuse + 16-sample Monte-Carlo specular with the hierarchical
 march) of the 1920x1080 synthetic scene (ground plane, 40 spheres, 60 boxes,
 512x256 lognormal(0, 2) environment; the paper's own data is not public).
@@ -60,29 +60,110 @@ def upload(scene, dtype, dev):
     return t
 
 
-def algorithmic_bytes(scene, hits, steps, dtype):
-    """Bytes the method itself reads and writes per frame (shading kernel and
-    pyramid build separately): per pixel the G-buffer record (depth 4 B plus
-    three 4-channel buffers minus the unused radiance channel: 48 B FP32,
-    26 B FP16/BF16) and the 12 B RGB output; per sample one 4 B depth or
-    pyramid texel per march iteration and one radiance read (12 B FP32 or
-    6 B FP16 at a hit pixel, 12 B for the environment otherwise); the pyramid
-    build reads the depth once and writes about a third of it."""
+# Algorithmic work model of one frame (the method's own reads, writes and
+# arithmetic; not what the implementation happens to issue).
+#
+# Bytes: every pixel's depth (4 B) and RGB output (12 B); a background pixel
+# one environment texel (12 B), any other pixel its two material records
+# (normal/roughness and albedo/metalness: 32 B FP32, 16 B FP16/BF16); per march
+# iteration the depth texels it reads (the hierarchical march reads the
+# (min, max) pair of a cell and of its parent: 16 B; the linear march one
+# depth: 4 B); per ray one radiance read (12 B FP32 or 6 B FP16 at a hit pixel,
+# 12 B of environment otherwise).  The pyramid build reads the depth once and
+# writes one pair per texel.
+#
+# Operations: 32-bit lane operations of the method's own formulation (an
+# FMA, a compare, a select, a transcendental instruction each count one):
+OPS_PER_HIZ_ITER = 54     # two cells (the cell and its parent), each: cell index 2,
+                          # exit parameter per axis 3 (x2), nearer exit 1, ray
+                          # inverse depth at the exit 1, texel address 2, front
+                          # test 1, behind test 2 (= 15, x2 = 30); level-0 test 6;
+                          # move / arm / level choice 8; advance 5; loop control 5
+OPS_PER_LINEAR_STEP = 20  # point 3, projection 5, bounds 4, texel address 3, tests 5
+OPS_PER_SAMPLE = 156      # Philox4x32-10 98 and the two 24-bit uniforms 6; the
+                          # visible-normal sample (stretch, normalise, cap point,
+                          # sin/cos, un-stretch, normalise) 30; to world 9;
+                          # reflection and the two cosines 13
+OPS_PER_RAY = 64          # ray segment (view direction 9, end point 8, projection
+                          # 10, screen deltas and inverse depths 8); Schlick
+                          # Fresnel 8, Smith G1 6, product 3; compensated sum 12
+OPS_PER_HIT = 2           # radiance texel address
+OPS_PER_MISS = 47         # equirect angles 25, texel coordinates 6, weights 4, blend 12
+OPS_PER_PIXEL = 132       # un-projection 3, view vector 17, normal 7, clamps 2, F0 3,
+                          # frame 10, local view vector 9; direct diffuse: level 3,
+                          # angles 25, two bilinear lookups 44, blend 3, albedo 4;
+                          # output 3
+# Peak: 157.3 TFLOP/s FP32 vector counts an FMA as two flops and a packed
+# instruction as two lanes; single 32-bit lane operations issue at
+# 256 CUs x 64 lanes x 2.4 GHz.
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+
+
+def work_model(scene, hits, steps, dtype):
+    """Algorithmic bytes and operations of the shading kernel and bytes of the
+    pyramid build, from the kernel's own hit codes and iteration counts."""
     P = scene.width * scene.height
-    bg = 48 if dtype == "f32" else 26
+    mat = 32 if dtype == "f32" else 16
     br_hit = 12 if dtype == "f32" else 6
     n_iter = int(steps.sum(dtype=np.int64))
-    valid = hits != -2
-    valid &= hits != -3
-    valid &= hits != -5
+    rays = (hits >= 0) | (hits == -1) | (hits == -4)  # samples that reach a radiance lookup
     n_hit = int((hits >= 0).sum())
-    n_env = int(valid.sum()) - n_hit
-    per_iter = 8 if scene.params["march"] == 1 else 4
-    shade = P * (bg + 12) + per_iter * n_iter + br_hit * n_hit + 12 * n_env
-    texels = sum(math.ceil(scene.width / 2 ** k) * math.ceil(scene.height / 2 ** k)
-                 for k in range(0, 15))
-    hiz = P * 4 + 8 * int(texels)
-    return shade, hiz, dict(mean_iters=n_iter / max(1, int(valid.sum())), hit_frac=n_hit / hits.size)
+    n_rays = int(rays.sum())
+    n_env = n_rays - n_hit
+    fg = int((hits[..., 0] != -3).sum())
+    hiz = scene.params["march"] == 1
+    shade_bytes = (P * 16 + fg * mat + (P - fg) * 12 + (16 if hiz else 4) * n_iter
+                   + br_hit * n_hit + 12 * n_env)
+    n_drawn = int((hits != -3).sum() - (hits == -5).sum())
+    shade_ops = ((OPS_PER_HIZ_ITER if hiz else OPS_PER_LINEAR_STEP) * n_iter
+                 + OPS_PER_SAMPLE * n_drawn + OPS_PER_RAY * n_rays + OPS_PER_HIT * n_hit
+                 + OPS_PER_MISS * n_env + OPS_PER_PIXEL * fg)
+    texels, w, h = 0, scene.width, scene.height
+    while True:
+        texels += w * h
+        if w == 1 and h == 1:
+            break
+        w, h = (w + 1) // 2, (h + 1) // 2
+    hiz_bytes = P * 4 + 8 * int(texels)
+    return dict(bytes_shade=shade_bytes, ops_shade=shade_ops, bytes_hiz=hiz_bytes,
+                mean_iters=n_iter / max(1, n_rays), hit_frac=n_hit / max(1, n_rays),
+                iterations=n_iter, rays=n_rays)
+
+
+COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "shade_hiz_kernel_c2_1080p_16spp_counters.md")
+
+
+def kernel_sources_digest():
+    """SHA-256 over the kernel sources, in name order."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_2504_01358_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(d)):
+        if name.endswith((".hip", ".h")):
+            with open(os.path.join(d, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the shading kernel from the committed counter
+    summary, or None when it is absent or was taken from other sources."""
+    try:
+        with open(COUNTER_SUMMARY) as f:
+            text = f.read()
+    except OSError:
+        return None
+    vals = {}
+    for ln in text.splitlines():
+        if "=" in ln and ln.strip().startswith(("traffic_bytes_per_launch", "sources_sha256")):
+            k, v = ln.strip().strip("`").split("=", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("sources_sha256") != kernel_sources_digest():
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def time_gpu(ctx, scene, dtype, steps, warmup, dev, mips):
@@ -133,11 +214,11 @@ def time_gpu(ctx, scene, dtype, steps, warmup, dev, mips):
     total_ms = start.elapsed_time(end)
     hiz_ms = [e[0].elapsed_time(e[1]) for e in evs]
     shade_ms = [e[1].elapsed_time(e[2]) for e in evs]
-    b_shade, b_hiz, extra = algorithmic_bytes(scene, hits_np, steps_np, dtype)
+    work = work_model(scene, hits_np, steps_np, dtype)
     return dict(ms_per_step=total_ms / steps, wall_ms_per_step=1e3 * wall / steps,
                 shade_ms=float(np.mean(shade_ms)), shade_ms_p50=float(np.median(shade_ms)),
                 shade_ms_p99=float(np.quantile(shade_ms, 0.99)), hiz_ms=float(np.mean(hiz_ms)),
-                bytes_shade=b_shade, bytes_hiz=b_hiz, **extra)
+                **work)
 
 
 def _oracle_rows(args):
@@ -225,7 +306,9 @@ def main():
         del src, dst, flush
     rays = scene.width * scene.height * scene.params["spp"]
     r32 = res["f32"]
-    achieved = r32["bytes_shade"] / (r32["shade_ms"] * 1e-3) / 1e9
+    kernel_s = r32["shade_ms"] * 1e-3
+    ops_rate = r32["ops_shade"] / kernel_s / 1e12
+    gbs = r32["bytes_shade"] / kernel_s / 1e9
     line = {
         "metric": "Mrays/s + ms/frame at 1080p 16spp (FP32 vs FP16 G-buf); p50/p99 serve latency",
         "value": rays / (r32["ms_per_step"] * 1e-3) / 1e6,
@@ -245,11 +328,16 @@ def main():
                                "G-buffer; plane + 40 spheres + 60 boxes; env 512x256 lognormal(0,2)",
                    "width": scene.width, "height": scene.height, "spp": scene.params["spp"],
                    "march": "hiz", "max_steps": scene.params["max_steps"]},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "shade_kernel<f32,hiz>",
-                     "kernel_ms": r32["shade_ms"], "algorithmic_bytes": r32["bytes_shade"],
-                     "mean_iterations_per_sample": r32["mean_iters"]},
+        "roofline": {"bound": "alu", "achieved": ops_rate, "peak": VALU_PEAK_TOPS,
+                     "unit": "Tops/s", "frac": ops_rate / VALU_PEAK_TOPS,
+                     "traffic": measured_traffic() if args.config == "c2" else None,
+                     "kernel": "shade_hiz_kernel<f32>", "kernel_ms": r32["shade_ms"],
+                     "algorithmic_ops": r32["ops_shade"],
+                     "march_iterations": r32["iterations"], "rays": r32["rays"],
+                     "mean_iterations_per_ray": r32["mean_iters"]},
+        "hbm": {"achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                "algorithmic_bytes": r32["bytes_shade"]},
+        "shade_ms_p50": r32["shade_ms_p50"], "shade_ms_p99": r32["shade_ms_p99"],
         "hiz_build_ms": r32["hiz_ms"],
     }
     for dt in ("f16", "bf16"):
