@@ -181,7 +181,7 @@ def time_gpu(ctx, scene, dtype, steps, warmup, dev, mips):
     def step(ev=None):
         if ev is not None:
             ev[0].record(stream)
-        ssr.hiz_build(t["depth"], out=hiz, stream=stream)
+        ssr.hiz_build(t["depth"], scene.params["thickness"], out=hiz, stream=stream)
         if ev is not None:
             ev[1].record(stream)
         ctx.shade(cam, t["depth"], t["normal_rough"], t["albedo_metal"], t["radiance"], t["env"],

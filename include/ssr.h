@@ -99,9 +99,10 @@ typedef struct {
     const void* radiance;     /* [H][W][4] (c1.r, c1.g, c1.b, unused): the
                                  first-pass radiance read at hit pixels         */
     int32_t dtype;            /* ssr_dtype of the three [H][W][4] buffers        */
-    const float* hiz;         /* NULL, or this depth buffer's min-max pyramid as
-                                 ssr_hiz_build wrote it (then ssr_shade does
-                                 not build it)                                   */
+    const float* hiz;         /* NULL, or the pyramid ssr_hiz_build wrote for this
+                                 depth buffer with the thickness of the
+                                 ssr_params it is shaded with (then ssr_shade
+                                 does not build it)                              */
 } ssr_gbuffer;
 
 typedef struct {
@@ -126,7 +127,7 @@ typedef struct {
 } ssr_params;
 
 /* Create a context on HIP device `device` (must be gfx950).  The context owns
- * a grow-only workspace (min-max depth pyramid, env mip chain).  *out is set to
+ * a grow-only workspace (depth pyramid, env mip chain).  *out is set to
  * NULL on failure. */
 int ssr_ctx_create(int device, ssr_ctx** out);
 
@@ -141,7 +142,7 @@ void ssr_ctx_destroy(ssr_ctx* ctx);
  * Sample s of pixel q = j*W + i draws Philox4x32-10 with counter
  * (q, s, frame, 0): u1 = (x0 >> 8) 2^-24 picks the azimuth, u2 = (x1 >> 8) 2^-24
  * the cap height of the visible-normal sample.  width or height 0 is a no-op.
- * In hiz mode the min-max depth pyramid is built in the context's workspace unless
+ * In hiz mode the depth pyramid is built in the context's workspace unless
  * gbuf->hiz supplies it; the env mip chain likewise unless env->mips does.
  * Both builds run on `stream` before the shading kernel. */
 int ssr_shade(ssr_ctx* ctx, const ssr_camera* cam, const ssr_gbuffer* gbuf,
@@ -159,20 +160,25 @@ int64_t ssr_env_mips_floats(int32_t width, int32_t height);
 int ssr_env_build_mips(const float* rgb, int32_t width, int32_t height, float* mips,
                        void* stream);
 
-/* Number of floats of the min-max depth pyramid of a W x H depth buffer (0 for
- * an empty or oversized image). */
+/* Number of floats of the depth pyramid of a W x H depth buffer (0 for an
+ * empty or oversized image). */
 int64_t ssr_hiz_floats(int32_t width, int32_t height);
 
-/* Fill `pyramid` (ssr_hiz_floats floats) with levels 0..top of the min-max
- * depth pyramid the hierarchical march traverses, in inverse depth: level 0
- * is W x H, level L has ceil(W_{L-1}/2) x ceil(H_{L-1}/2) texels and the last
- * level is 1 x 1.  Each texel is the pair (1/min D, 1/max D) over the pixels it
- * covers (level 0: (1/D, 1/D); background: 0), the correctly rounded float32
- * quotients, stored as two floats, row-major, level after level.  Depths must
- * be positive.  Pass the buffer to ssr_shade through ssr_gbuffer.hiz to reuse
- * it. */
-int ssr_hiz_build(const float* depth, int32_t width, int32_t height, float* pyramid,
-                  void* stream);
+/* Fill `pyramid` (ssr_hiz_floats floats) with levels 0..top of the depth
+ * pyramid the hierarchical march traverses (Appendix D, the hierarchical
+ * variant), in inverse depth over each pixel's hit slab [D, D + thickness]:
+ * level 0 is W x H, level L has ceil(W_{L-1}/2) x ceil(H_{L-1}/2) texels and
+ * the last level is 1 x 1.  A level-0 texel is the pair
+ * (1/D, 1/(D + thickness)), both correctly rounded float32 quotients (with
+ * D + thickness rounded first); a texel above holds the maximum of the first
+ * and the minimum of the second over its children, i.e. one over the
+ * smallest depth and one over the largest depth plus thickness of the pixels
+ * it covers.  Background (D = +inf) gives (0, 0).  Stored as two floats,
+ * row-major, level after level.  Depths must be positive, thickness finite
+ * and >= 0 (else SSR_E_ARG).  Pass the buffer to ssr_shade through
+ * ssr_gbuffer.hiz to reuse it with the same thickness. */
+int ssr_hiz_build(const float* depth, int32_t width, int32_t height, float thickness,
+                  float* pyramid, void* stream);
 
 /* Philox4x32-10 (Salmon et al., SC'11) of n counters: ctr [n][4], key [n][2],
  * out [n][4], all uint32 device buffers.  The same generator ssr_shade draws

@@ -139,11 +139,12 @@ int64_t ssr_hiz_floats(int32_t width, int32_t height) {
     return 2 * lay.total;
 }
 
-int ssr_hiz_build(const float* depth, int32_t width, int32_t height, float* pyramid,
-                  void* stream) {
+int ssr_hiz_build(const float* depth, int32_t width, int32_t height, float thickness,
+                  float* pyramid, void* stream) {
     ssr::HizLayout lay;
     if (!depth || !pyramid || !ssr::make_hiz_layout(width, height, &lay)) return SSR_E_ARG;
-    return hip_status(ssr::launch_hiz(depth, lay, reinterpret_cast<float2*>(pyramid),
+    if (!(thickness >= 0.0f) || !finite_f(thickness)) return SSR_E_ARG;
+    return hip_status(ssr::launch_hiz(depth, lay, thickness, reinterpret_cast<float2*>(pyramid),
                                       static_cast<hipStream_t>(stream)));
 }
 
@@ -187,7 +188,7 @@ int ssr_shade(ssr_ctx* ctx, const ssr_camera* cam, const ssr_gbuffer* g, const s
     if (p->march == SSR_MARCH_HIZ && !hiz) {
         st = ensure(&ctx->hiz, &ctx->hiz_cap, hiz_lay.total);
         if (st != SSR_OK) return st;
-        st = hip_status(ssr::launch_hiz(g->depth, hiz_lay, ctx->hiz, s));
+        st = hip_status(ssr::launch_hiz(g->depth, hiz_lay, p->thickness, ctx->hiz, s));
         if (st != SSR_OK) return st;
         hiz = ctx->hiz;
     }

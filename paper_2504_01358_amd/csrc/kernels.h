@@ -45,7 +45,7 @@ struct ShadeArgs {
     const void* radiance;
     const float4* env;        // mip chain (EnvLayout)
     EnvLayout env_lay;
-    const float2* hiz;        // min-max pyramid (HizLayout)
+    const float2* hiz;        // slab pyramid (HizLayout): (1/min D, 1/max(D + thickness))
     HizLayout hiz_lay;
     int spp, max_steps, linear_samples;
     float step_len, max_dist, thickness;
@@ -57,7 +57,7 @@ struct ShadeArgs {
 
 hipError_t launch_env_mips(const float* rgb, const EnvLayout& lay, float4* mips,
                            hipStream_t stream);
-hipError_t launch_hiz(const float* depth, const HizLayout& lay, float2* pyramid,
+hipError_t launch_hiz(const float* depth, const HizLayout& lay, float thickness, float2* pyramid,
                       hipStream_t stream);
 hipError_t launch_shade(const ShadeArgs& args, int dtype, int march, hipStream_t stream);
 hipError_t launch_philox(const uint32_t* ctr, const uint32_t* key, int64_t n, uint32_t* out,

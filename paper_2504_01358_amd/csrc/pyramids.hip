@@ -1,12 +1,14 @@
 // Builders for the two pyramids the shading kernel reads:
 //  * the environment mip chain (Sec. 3.2, SampleEnvMap at level lambda):
 //    level k is the 2x2 box mean of level k-1;
-//  * the depth pyramid used by the hierarchical march, kept in inverse depth:
-//    a level-0 texel is (1/D, 1/D) and a level-L texel holds the maximum and
-//    minimum inverse depth of its (up to four) level L-1 children (that is,
-//    one over the minimum and one over the maximum depth of the pixels it
-//    covers), ceil-halving to 1 x 1.  A background pixel (D = +inf) has
-//    inverse depth 0.
+//  * the depth pyramid used by the hierarchical march, kept in inverse depth
+//    over the hit slab [D, D + thickness] of each pixel: a level-0 texel is
+//    (1/D, 1/(D + thickness)), the near and the far side of the slab, and a
+//    level-L texel holds the maximum of the first and the minimum of the
+//    second over its (up to four) level L-1 children (that is, one over the
+//    minimum depth and one over the maximum depth plus thickness of the
+//    pixels it covers), ceil-halving to 1 x 1.  A background pixel
+//    (D = +inf) has inverse depth 0 on both sides.
 #include "device_math.h"
 #include "kernels.h"
 
@@ -84,15 +86,16 @@ hipError_t launch_env_mips(const float* rgb, const EnvLayout& lay, float4* mips,
 // ------------------------------------------------------------ Hi-Z pyramid --
 //
 // Pass 1: one 256-thread workgroup per 64 x 64 depth tile writes levels 0..6
-// of that tile.  Each thread reduces a 4 x 4 pixel block to its (1/D, 1/D)
-// level-0 pairs, two level-1 rows and one level-2 texel in registers; the
-// 16 x 16 level-2 texels go through LDS for levels 3..6.  A texel at level L
-// is the (max, min) inverse depth of the 2^L x 2^L pixel block it covers,
-// clipped to the image (pixels outside count as -inf for the max and +inf
-// for the min), which equals the ceil-halving recursion.  Texels that do not
-// exist at their level (index >= W_L or H_L) are not written.  1/D is the
-// correctly rounded quotient, and rounding is monotone, so a texel equals
-// the rounded inverse of the block's minimum and maximum depth exactly.
+// of that tile.  Each thread reduces a 4 x 4 pixel block to its
+// (1/D, 1/(D + thickness)) level-0 pairs, two level-1 rows and one level-2
+// texel in registers; the 16 x 16 level-2 texels go through LDS for levels
+// 3..6.  A texel at level L is the (max, min) of those pairs over the
+// 2^L x 2^L pixel block it covers, clipped to the image (pixels outside
+// count as -inf for the max and +inf for the min), which equals the
+// ceil-halving recursion.  Texels that do not exist at their level
+// (index >= W_L or H_L) are not written.  Both quotients are correctly
+// rounded and rounding is monotone, so a texel equals the rounded inverse of
+// the block's minimum depth and of its maximum (depth + thickness) exactly.
 //
 // Pass 2: the levels above 6.  When level 6 fits in LDS, one workgroup does
 // them all there; otherwise one launch per level from global memory.
@@ -107,7 +110,7 @@ __device__ __forceinline__ float2 mm(float2 a, float2 b) {
 
 __global__ __launch_bounds__(256) void hiz_tile_kernel(const float* __restrict__ depth,
                                                        float2* __restrict__ pyr, HizLayout lay,
-                                                       int tile_levels) {
+                                                       float thickness, int tile_levels) {
     __shared__ float2 lds[2][16 * 16];
     const int W = lay.w[0], H = lay.h[0];
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
@@ -121,8 +124,9 @@ __global__ __launch_bounds__(256) void hiz_tile_kernel(const float* __restrict__
         for (int c = 0; c < 4; ++c) {
             const int x = x0 + c;
             const bool in = x < W && y < H;
-            const float iz = in ? 1.0f / depth[static_cast<int64_t>(y) * W + x] : 0.0f;
-            p[r][c] = in ? make_float2(iz, iz) : make_float2(-INFINITY, INFINITY);
+            const float D = in ? depth[static_cast<int64_t>(y) * W + x] : 1.0f;
+            p[r][c] = in ? make_float2(1.0f / D, 1.0f / (D + thickness))
+                         : make_float2(-INFINITY, INFINITY);
             if (in) pyr[static_cast<int64_t>(y) * W + x] = p[r][c];
         }
     }
@@ -213,12 +217,12 @@ __global__ __launch_bounds__(1024) void hiz_top_kernel(float2* __restrict__ pyr,
     }
 }
 
-hipError_t launch_hiz(const float* depth, const HizLayout& lay, float2* pyramid,
+hipError_t launch_hiz(const float* depth, const HizLayout& lay, float thickness, float2* pyramid,
                       hipStream_t stream) {
     const int top = lay.levels - 1;
     const int tile_levels = top < kTileLevels ? top : kTileLevels;
     const dim3 grid((lay.w[0] + kTile - 1) / kTile, (lay.h[0] + kTile - 1) / kTile);
-    hipLaunchKernelGGL(hiz_tile_kernel, grid, dim3(256), 0, stream, depth, pyramid, lay,
+    hipLaunchKernelGGL(hiz_tile_kernel, grid, dim3(256), 0, stream, depth, pyramid, lay, thickness,
                        tile_levels);
     if (top > kTileLevels) {
         const int first = kTileLevels + 1;

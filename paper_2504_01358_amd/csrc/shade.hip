@@ -100,29 +100,27 @@ __device__ __forceinline__ MarchResult march_linear(const ShadeArgs& a, int i, i
 
 // ------------------------------------------------------ hierarchical march --
 //
-// Exact first hit on the depth heightfield, hierarchical over the min-max
+// Exact first hit on the depth heightfield, hierarchical over the depth
 // pyramid.  The ray is clipped at max_dist and the near plane and projected
 // to the screen segment P0 + s dP.  Its inverse depth iz(s) = iz0 + s diz is
 // linear in s (perspective-correct interpolation), so the march runs in
-// inverse depth and needs no division: the pyramid holds (1/min D, 1/max D)
-// per cell.  A cell can be skipped when the ray's part inside it lies wholly
-// in front of the cell's nearest surface (its smallest inverse depth exceeds
-// 1/min D) or wholly behind the cell's farthest surface plus the thickness
-// (largest inverse depth b with b (1 + th/max D) < 1/max D).  Each iteration
-// looks at the level-L cell and its parent at once (two independent 8 B
-// gathers): skip the parent and go up a level, else skip the cell, else go
-// down two levels, else (level 0) test the pixel and step to the next one.
+// inverse depth and needs no division: the pyramid holds, per cell, one over
+// the nearest depth and one over the farthest depth plus the thickness, the
+// two sides of the union of the cell's hit slabs.  A cell can be skipped when
+// the ray's part inside it lies wholly in front of that union (its smallest
+// inverse depth exceeds the first) or wholly behind it (its largest inverse
+// depth is below the second).  Each iteration looks at the level-L cell and
+// its parent at once (two independent 8 B gathers): skip the parent and go
+// up a level, else skip the cell, else go down two levels, else (level 0)
+// test the pixel and step to the next one.
 //
 // The march is resumable (one iteration per call) so that a wave can keep
 // all its lanes busy with rays of different lengths.
 
-// Everything a ray needs for its march: the segment, computed when the ray is
-// drawn, and its extent, computed when a lane starts marching it.
+// The part of a ray computed when it is drawn (and queued).
 struct HizSegment {
     bool valid;             // false: clipped away before it started (code -1, 0 iterations)
     float dPx, dPy;         // P1 - P0 in pixels
-    float inv_dx, inv_dy;   // 1 / dP (+inf for a zero component)
-    float s_max;            // where the segment leaves the screen (at most 1)
     float iz0, diz;         // inverse depth at s = 0 and its change over the segment
 };
 
@@ -140,40 +138,47 @@ __device__ __forceinline__ HizSegment hiz_segment(const ShadeArgs& a, int i, int
     return g;
 }
 
-// The per-axis reciprocals and the screen exit of a segment.  A zero
-// component counts as travelling in the positive direction: its far boundary
-// is then never reached (s = +inf).
-__device__ __forceinline__ void hiz_extent(const ShadeArgs& a, int i, int j, HizSegment& g) {
-    const float P0x = static_cast<float>(i) + 0.5f, P0y = static_cast<float>(j) + 0.5f;
-    g.inv_dx = g.dPx != 0.0f ? 1.0f / g.dPx : INFINITY;
-    g.inv_dy = g.dPy != 0.0f ? 1.0f / g.dPy : INFINITY;
-    const float Wf = static_cast<float>(a.W), Hf = static_cast<float>(a.H);
-    g.s_max = fminf(fminf(((g.dPx >= 0.0f ? Wf : 0.0f) - P0x) * g.inv_dx,
-                          ((g.dPy >= 0.0f ? Hf : 0.0f) - P0y) * g.inv_dy),
-                    1.0f);
-}
-
+// A ray being marched.  A boundary x = b is crossed at s = b inv_dx + bx.  A
+// zero component of dP counts as travelling in the positive direction with
+// inv = +inf: its crossings are then NaN, which fminf ignores, and the far
+// screen edge is never reached.
 struct HizRay {
     int i, j;             // origin pixel
     float P0x, P0y;       // its centre
-    float bx, by;         // -P0 / dP: a boundary b is crossed at s = b / dP + bx
-    HizSegment g;
+    float dPx, dPy;
+    float inv_dx, inv_dy; // 1 / dP
+    float bx, by;         // -P0 / dP
+    int xp, yp;           // 1 when travelling toward +x (+y), else 0
+    float s_max;          // where the segment leaves the screen (at most 1)
+    float iz0, diz;
     float s, iz_in;       // current point of the segment and the ray's inverse depth there
     int L, ix, iy;        // level and the level-0 pixel containing the current point
     bool armed;           // the ray has been in front of the depth buffer
     int it;               // iterations so far
 };
 
-__device__ __forceinline__ void hiz_start(HizRay& r, int i, int j, const HizSegment& g) {
+__device__ __forceinline__ void hiz_start(const ShadeArgs& a, HizRay& r, int i, int j, float dPx,
+                                          float dPy, float iz0, float diz) {
     r.i = i;
     r.j = j;
     r.P0x = static_cast<float>(i) + 0.5f;
     r.P0y = static_cast<float>(j) + 0.5f;
-    r.bx = -r.P0x * g.inv_dx;
-    r.by = -r.P0y * g.inv_dy;
-    r.g = g;
+    r.dPx = dPx;
+    r.dPy = dPy;
+    // (the hardware reciprocal: the crossings need not be correctly rounded)
+    r.inv_dx = dPx != 0.0f ? __builtin_amdgcn_rcpf(dPx) : INFINITY;
+    r.inv_dy = dPy != 0.0f ? __builtin_amdgcn_rcpf(dPy) : INFINITY;
+    r.xp = dPx >= 0.0f ? 1 : 0;
+    r.yp = dPy >= 0.0f ? 1 : 0;
+    r.bx = -r.P0x * r.inv_dx;
+    r.by = -r.P0y * r.inv_dy;
+    r.s_max = fminf(fminf(fmaf(r.xp ? static_cast<float>(a.W) : 0.0f, r.inv_dx, r.bx),
+                          fmaf(r.yp ? static_cast<float>(a.H) : 0.0f, r.inv_dy, r.by)),
+                    1.0f);
+    r.iz0 = iz0;
+    r.diz = diz;
     r.s = 0.0f;
-    r.iz_in = g.iz0;
+    r.iz_in = iz0;
     r.L = 0;
     r.ix = i;
     r.iy = j;
@@ -181,65 +186,66 @@ __device__ __forceinline__ void hiz_start(HizRay& r, int i, int j, const HizSegm
     r.it = 0;
 }
 
-// One iteration, branch-free.  Returns true when the ray is finished, with
-// its hit code.  `lvl[L]` holds (offset, width) of level L and of level
-// min(L + 1, top).
-__device__ __forceinline__ bool hiz_step(const ShadeArgs& a, const int4* lvl, HizRay& r, int& code) {
-    const int top = a.hiz_lay.levels - 1;
-    const int L = r.L, Lp = min(L + 1, top);
+// One iteration, branch-free.  Returns true when the ray is finished; then
+// `hit` tells a hit at (ix, iy) from leaving the screen or the segment (or
+// the iteration cap, which the caller tells by r.it).  `lvl[L]` holds
+// (offset, width) of level L and of its parent; the top level's parent is the
+// top texel again with width 0, so the look-ahead needs no special case there
+// (skipping it means leaving the screen, as skipping the top cell does).
+__device__ __forceinline__ bool hiz_step(const ShadeArgs& a, const int4* lvl, HizRay& r, bool& hit,
+                                         bool& leave) {
+    const int L = r.L, Lp = L + 1;
     ++r.it;
     const int4 lv = lvl[L];
-    // 32-bit byte offsets from a base held in SGPRs (the pyramid is < 4 GiB)
+    const int cx = r.ix >> L, cy = r.iy >> L, px = r.ix >> Lp, py = r.iy >> Lp;
+    // 32-bit byte offsets from a base held in SGPRs (the pyramid is < 4 GiB;
+    // row index and width are below 2^14, so the 24-bit multiply is exact)
     const char* base = reinterpret_cast<const char*>(a.hiz);
-    // (row index and width are below 2^14: the 24-bit multiply is exact)
-    const unsigned oc = (lv.x + __umul24(r.iy >> L, lv.y) + (r.ix >> L)) << 3;
-    const unsigned op = (lv.z + __umul24(r.iy >> Lp, lv.w) + (r.ix >> Lp)) << 3;
-    const float2 zc = *reinterpret_cast<const float2*>(base + oc);   // (1/min D, 1/max D)
+    const unsigned oc = (lv.x + __umul24(cy, lv.y) + cx) << 3;
+    const unsigned op = (lv.z + __umul24(py, lv.w) + px) << 3;
+    const float2 zc = *reinterpret_cast<const float2*>(base + oc);  // (1/min D, 1/max(D + th))
     const float2 zp = *reinterpret_cast<const float2*>(base + op);
-    const bool xpos = r.g.dPx >= 0.0f, ypos = r.g.dPy >= 0.0f;
-    // the level-L cell and its parent: bounds and where the segment leaves them
-    const int szc = 1 << L, szp = 1 << Lp;
-    const int cx0 = r.ix & -szc, cy0 = r.iy & -szc, px0 = r.ix & -szp, py0 = r.iy & -szp;
-    const int cx1 = min(cx0 + szc, a.W), cy1 = min(cy0 + szc, a.H);
-    const int px1 = min(px0 + szp, a.W), py1 = min(py0 + szp, a.H);
-    const float sxc = fmaf(static_cast<float>(xpos ? cx1 : cx0), r.g.inv_dx, r.bx);
-    const float syc = fmaf(static_cast<float>(ypos ? cy1 : cy0), r.g.inv_dy, r.by);
-    const float sxp = fmaf(static_cast<float>(xpos ? px1 : px0), r.g.inv_dx, r.bx);
-    const float syp = fmaf(static_cast<float>(ypos ? py1 : py0), r.g.inv_dy, r.by);
-    const float sec = fminf(fminf(sxc, syc), r.g.s_max), sep = fminf(fminf(sxp, syp), r.g.s_max);
-    const float izc = r.g.iz0 + sec * r.g.diz, izp = r.g.iz0 + sep * r.g.diz;
+    // the boundaries the segment leaves the cell and the parent through
+    const int ecx = (cx + r.xp) << L, ecy = (cy + r.yp) << L;
+    const int epx = (px + r.xp) << Lp, epy = (py + r.yp) << Lp;
+    const float sxc = fmaf(static_cast<float>(ecx), r.inv_dx, r.bx);
+    const float syc = fmaf(static_cast<float>(ecy), r.inv_dy, r.by);
+    const float sxp = fmaf(static_cast<float>(epx), r.inv_dx, r.bx);
+    const float syp = fmaf(static_cast<float>(epy), r.inv_dy, r.by);
+    const float sec = fminf(fminf(sxc, syc), r.s_max), sep = fminf(fminf(sxp, syp), r.s_max);
+    const float izc = fmaf(sec, r.diz, r.iz0), izp = fmaf(sep, r.diz, r.iz0);
     // far end (smaller inverse depth) and near end of the ray inside each cell
     const float fc = fminf(r.iz_in, izc), nc = fmaxf(r.iz_in, izc);
     const float fp = fminf(r.iz_in, izp), np = fmaxf(r.iz_in, izp);
-    const float th = a.thickness;
     const bool front_c = fc > zc.x;
-    const bool skip_c = front_c | (nc * fmaf(th, zc.y, 1.0f) < zc.y);
+    const bool skip_c = front_c | (nc < zc.y);
     const bool front_p = fp > zp.x;
-    const bool up = (L < top) & (front_p | (np * fmaf(th, zp.y, 1.0f) < zp.y));
+    const bool up = front_p | (np < zp.y);
     // outcomes: skip the parent / skip the cell / go down / level-0 pixel
     const bool stay = !up & !skip_c;
     const bool at0 = L == 0;
     const bool test = stay & at0 & ((r.ix != r.i) | (r.iy != r.j));
-    const bool hit = test & (r.armed | (r.iz_in > zc.x));
+    hit = test & (r.armed | (r.iz_in > zc.x));
     const bool move = !hit & (!stay | at0);
     // the cell the segment moves across
     const float se = up ? sep : sec;
     const float sx = up ? sxp : sxc, sy = up ? syp : syc;
-    const int x0 = up ? px0 : cx0, x1 = up ? px1 : cx1, y0 = up ? py0 : cy0, y1 = up ? py1 : cy1;
+    const int ex = up ? epx : ecx, ey = up ? epy : ecy;
     r.armed = r.armed | (move & (up ? front_p : front_c) & !stay & (se > r.s)) | (test & (nc > zc.x));
-    // the pixel on the far side of the crossed boundary (both axes at a corner)
-    const int fx = min(max(static_cast<int>(floorf(fmaf(se, r.g.dPx, r.P0x))), x0), x1 - 1);
-    const int fy = min(max(static_cast<int>(floorf(fmaf(se, r.g.dPy, r.P0y))), y0), y1 - 1);
-    const int nx = sx == se ? (xpos ? x1 : x0 - 1) : fx;
-    const int ny = sy == se ? (ypos ? y1 : y0 - 1) : fy;
-    const bool leave = move & ((se >= r.g.s_max) | (nx < 0) | (nx >= a.W) | (ny < 0) | (ny >= a.H));
+    // the pixel on the far side of the crossed boundary: on a crossed axis the
+    // first pixel past it, on the other axis the pixel the point lies in
+    const bool kx = sx == se, ky = sy == se;
+    const int v = static_cast<int>(floorf(fmaf(se, kx ? r.dPy : r.dPx, kx ? r.P0y : r.P0x)));
+    const int nx = kx ? ex + r.xp - 1 : v;
+    const int ny = ky ? ey + r.yp - 1 : v;
+    leave = move & ((se >= r.s_max) | (static_cast<unsigned>(nx) >= static_cast<unsigned>(a.W)) |
+                    (static_cast<unsigned>(ny) >= static_cast<unsigned>(a.H)));
     const bool step = move & !leave;
     r.ix = step ? nx : r.ix;
     r.iy = step ? ny : r.iy;
     r.s = step ? se : r.s;
     r.iz_in = step ? (up ? izp : izc) : r.iz_in;
-    r.L = (step & up) ? min(L + 1, top) : ((stay & !at0) ? max(L - 2, 0) : L);
-    code = hit ? r.iy * a.W + r.ix : (leave ? SSR_HIT_OFFSCREEN : SSR_HIT_CAP);
+    r.L = (step & up) ? Lp : ((stay & !at0) ? max(L - 2, 0) : L);
     return hit | leave | (r.it >= a.max_steps);
 }
 
@@ -374,9 +380,9 @@ __device__ __forceinline__ int fill_code(const ShadeArgs& a, const Pixel& P) {
 
 __device__ __forceinline__ void write_out(const ShadeArgs& a, int64_t q, float3 cd, const float* sum) {
     const float invS = 1.0f / static_cast<float>(a.spp);
-    a.out[3 * q + 0] = cd.x + sum[0] * invS;
-    a.out[3 * q + 1] = cd.y + sum[1] * invS;
-    a.out[3 * q + 2] = cd.z + sum[2] * invS;
+    // one 12-byte store per pixel: a row of lanes writes one contiguous run
+    reinterpret_cast<float3*>(a.out)[q] =
+        make_float3(cd.x + sum[0] * invS, cd.y + sum[1] * invS, cd.z + sum[2] * invS);
 }
 
 // -------------------------------------------------- linear-march kernel --
@@ -451,9 +457,10 @@ void shade_hiz_kernel(const ShadeArgs a) {
     {
         const int nl = a.hiz_lay.levels;
         if (lane < nl) {
-            const int Lp = min(lane + 1, nl - 1);
-            lvl[lane] = make_int4(a.hiz_lay.offset[lane], a.hiz_lay.w[lane], a.hiz_lay.offset[Lp],
-                                  a.hiz_lay.w[Lp]);
+            const bool top = lane == nl - 1;
+            lvl[lane] = make_int4(a.hiz_lay.offset[lane], a.hiz_lay.w[lane],
+                                  a.hiz_lay.offset[top ? lane : lane + 1],
+                                  top ? 0 : a.hiz_lay.w[lane + 1]);
         }
     }
     const int tiles_x = (a.W + 7) / 8;
@@ -519,24 +526,17 @@ void shade_hiz_kernel(const ShadeArgs a) {
                         const float4 gq = q_seg[qh + rank];
                         slot = q_slot[qh + rank];
                         const int ln = slot & 63;
-                        const int ri = ti + (ln & 7), rj = tj + (ln >> 3);
-                        HizSegment g;
-                        g.valid = true;
-                        g.dPx = gq.x;
-                        g.dPy = gq.y;
-                        g.iz0 = gq.z;
-                        g.diz = gq.w;
-                        hiz_extent(a, ri, rj, g);
-                        hiz_start(r, ri, rj, g);
+                        hiz_start(a, r, ti + (ln & 7), tj + (ln >> 3), gq.x, gq.y, gq.z, gq.w);
                         active = true;
                     }
                     qh += min(nidle, rem);
                 }
                 if (!__any(active)) break;
                 if (active) {
-                    int code;
-                    if (hiz_step(a, lvl, r, code)) {
-                        r_code[slot] = code;
+                    bool hit, leave;
+                    if (hiz_step(a, lvl, r, hit, leave)) {
+                        r_code[slot] = hit ? r.iy * a.W + r.ix
+                                           : (leave ? SSR_HIT_OFFSCREEN : SSR_HIT_CAP);
                         r_iters[slot] = r.it;
                         active = false;
                     }

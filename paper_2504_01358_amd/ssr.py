@@ -74,7 +74,7 @@ def _load():
     lib.ssr_env_build_mips.restype = ctypes.c_int
     lib.ssr_hiz_floats.argtypes = [ctypes.c_int32, ctypes.c_int32]
     lib.ssr_hiz_floats.restype = ctypes.c_int64
-    lib.ssr_hiz_build.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, vp, vp]
+    lib.ssr_hiz_build.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_float, vp, vp]
     lib.ssr_hiz_build.restype = ctypes.c_int
     lib.ssr_philox4x32_10.argtypes = [vp, vp, ctypes.c_int64, vp, vp]
     lib.ssr_philox4x32_10.restype = ctypes.c_int
@@ -227,8 +227,9 @@ def hiz_floats(width, height) -> int:
     return int(lib.ssr_hiz_floats(int(width), int(height)))
 
 
-def hiz_build(depth, out=None, stream=None):
-    """Min-max pyramid (levels 0..top, (min, max) float pairs) of ``depth`` [H][W]."""
+def hiz_build(depth, thickness, out=None, stream=None):
+    """Depth pyramid of ``depth`` [H][W] for hit slabs of the given thickness:
+    levels 0..top of (1/min D, 1/max(D + thickness)) float pairs."""
     _dev_tensor(depth, "depth", torch.float32)
     H, W = depth.shape
     n = hiz_floats(W, H)
@@ -237,8 +238,8 @@ def hiz_build(depth, out=None, stream=None):
     if out is None:
         out = torch.empty(n, dtype=torch.float32, device=depth.device)
     _dev_tensor(out, "out", torch.float32, (n,))
-    _check(lib.ssr_hiz_build(_ptr(depth), W, H, _ptr(out), _stream(stream, depth.device)),
-           "ssr_hiz_build")
+    _check(lib.ssr_hiz_build(_ptr(depth), W, H, float(thickness), _ptr(out),
+                             _stream(stream, depth.device)), "ssr_hiz_build")
     return out
 
 

@@ -105,7 +105,7 @@ def test_host_side_argument_checks(lib):
     # null context / structures: rejected before any device work
     assert raw.ssr_shade(None, byref(cam), byref(g), byref(e), byref(p), None, None, None, None) == -1
     assert raw.ssr_env_build_mips(None, 512, 256, None, None) == -1
-    assert raw.ssr_hiz_build(None, 16, 16, None, None) == -1
+    assert raw.ssr_hiz_build(None, 16, 16, 0.0, None, None) == -1
     assert raw.ssr_philox4x32_10(None, None, 0, None, None) == 0
     assert raw.ssr_philox4x32_10(None, None, 5, None, None) == -1
     assert raw.ssr_philox4x32_10(None, None, -1, None, None) == -1

@@ -65,23 +65,33 @@ def test_philox_bit_exact():
     assert np.array_equal(got, want)
 
 
-@pytest.mark.parametrize("h,w", [(1, 1), (1, 5), (7, 3), (64, 64), (65, 129), (135, 241),
-                                 (1080, 1920), (2160, 3840), (17, 4099)])
-def test_hiz_pyramid_bit_exact(h, w):
+@pytest.mark.parametrize("h,w,th", [(1, 1, 0.0), (1, 5, 0.05), (7, 3, 1.0), (64, 64, 0.05),
+                                    (65, 129, 0.0), (135, 241, 0.3), (1080, 1920, 0.05),
+                                    (2160, 3840, 0.05), (17, 4099, 2.5)])
+def test_hiz_pyramid_bit_exact(h, w, th):
     from paper_2504_01358_amd import ssr
     rng = np.random.default_rng(h * 7 + w)
     d = rng.uniform(0.5, 50, (h, w)).astype(np.float32)
     d[rng.uniform(size=(h, w)) < 0.1] = np.inf
-    got = ssr.hiz_build(torch.from_numpy(d).cuda()).cpu().numpy().reshape(-1, 2)
+    got = ssr.hiz_build(torch.from_numpy(d).cuda(), th).cpu().numpy().reshape(-1, 2)
     mins = oracle.march.hiz_pyramid(d)
     maxs = oracle.march.hiz_max_pyramid(d)
-    one = np.float32(1.0)
-    # stored as correctly rounded float32 inverse depths (1/min, 1/max)
+    one, t32 = np.float32(1.0), np.float32(th)
+    # stored as correctly rounded float32 quotients (1/min D, 1/(max D + th)),
+    # the sum rounded to float32 first
     want = np.concatenate([np.stack([one / a.reshape(-1).astype(np.float32),
-                                     one / b.reshape(-1).astype(np.float32)], 1)
+                                     one / (b.reshape(-1).astype(np.float32) + t32)], 1)
                            for a, b in zip(mins, maxs)])
     assert got.shape == want.shape
     assert np.array_equal(got, want)
+
+
+def test_hiz_build_rejects_bad_thickness():
+    from paper_2504_01358_amd import ssr
+    d = torch.ones((4, 4), dtype=torch.float32, device="cuda")
+    for th in (-0.1, float("nan"), float("inf")):
+        with pytest.raises(ssr.SSRError):
+            ssr.hiz_build(d, th)
 
 
 @pytest.mark.parametrize("he", [1, 2, 32, 256])
@@ -260,7 +270,7 @@ def test_deterministic_and_prebuilt_mips(ctx):
     a, _ = run_gpu(ctx, sc.camera, gbuf_of(sc), sc.env, sc.params)
     b, _ = run_gpu(ctx, sc.camera, gbuf_of(sc), sc.env, sc.params)
     mips = ssr.env_build_mips(torch.from_numpy(sc.env).cuda())
-    hiz = ssr.hiz_build(torch.from_numpy(sc.depth).cuda())
+    hiz = ssr.hiz_build(torch.from_numpy(sc.depth).cuda(), sc.params["thickness"])
     c, _ = run_gpu(ctx, sc.camera, gbuf_of(sc), sc.env, sc.params, env_mips=mips, hiz=hiz)
     for k in ("out", "hits", "steps"):
         assert np.array_equal(a[k], b[k]) and np.array_equal(a[k], c[k])
