@@ -124,7 +124,7 @@ def work_model(scene, hits, steps, dtype):
         if w == 1 and h == 1:
             break
         w, h = (w + 1) // 2, (h + 1) // 2
-    hiz_bytes = P * 4 + 8 * int(texels)
+    hiz_bytes = P * 4 + 16 * int(texels)
     return dict(bytes_shade=shade_bytes, ops_shade=shade_ops, bytes_hiz=hiz_bytes,
                 mean_iters=n_iter / max(1, n_rays), hit_frac=n_hit / max(1, n_rays),
                 iterations=n_iter, rays=n_rays)

@@ -161,22 +161,26 @@ int ssr_env_build_mips(const float* rgb, int32_t width, int32_t height, float* m
                        void* stream);
 
 /* Number of floats of the depth pyramid of a W x H depth buffer (0 for an
- * empty or oversized image). */
+ * empty image, or one whose pyramid would exceed 4 GiB: about 200 Mpixels,
+ * beyond which the hierarchical march is unavailable and ssr_shade returns
+ * SSR_E_ARG for it). */
 int64_t ssr_hiz_floats(int32_t width, int32_t height);
 
 /* Fill `pyramid` (ssr_hiz_floats floats) with levels 0..top of the depth
  * pyramid the hierarchical march traverses (Appendix D, the hierarchical
  * variant), in inverse depth over each pixel's hit slab [D, D + thickness]:
  * level 0 is W x H, level L has ceil(W_{L-1}/2) x ceil(H_{L-1}/2) texels and
- * the last level is 1 x 1.  A level-0 texel is the pair
+ * the last level is 1 x 1.  The pair of a level-0 texel is
  * (1/D, 1/(D + thickness)), both correctly rounded float32 quotients (with
- * D + thickness rounded first); a texel above holds the maximum of the first
- * and the minimum of the second over its children, i.e. one over the
- * smallest depth and one over the largest depth plus thickness of the pixels
- * it covers.  Background (D = +inf) gives (0, 0).  Stored as two floats,
- * row-major, level after level.  Depths must be positive, thickness finite
- * and >= 0 (else SSR_E_ARG).  Pass the buffer to ssr_shade through
- * ssr_gbuffer.hiz to reuse it with the same thickness. */
+ * D + thickness rounded first); the pair of a texel above holds the maximum
+ * of the first and the minimum of the second over its children, i.e. one
+ * over the smallest depth and one over the largest depth plus thickness of
+ * the pixels it covers.  Background (D = +inf) gives (0, 0).  Each texel is
+ * stored as four floats, its own pair and then the pair of its parent (the
+ * texel (x/2, y/2) one level up; the top texel repeats its own), row-major,
+ * level after level.  Depths must be positive, thickness finite and >= 0
+ * (else SSR_E_ARG).  Pass the buffer to ssr_shade through ssr_gbuffer.hiz to
+ * reuse it with the same thickness. */
 int ssr_hiz_build(const float* depth, int32_t width, int32_t height, float thickness,
                   float* pyramid, void* stream);
 

@@ -10,11 +10,16 @@
 
 struct ssr_ctx {
     int device;
-    // workspace: min-max depth pyramid and env mip chain
-    float2* hiz;
-    int64_t hiz_cap;    // float2 texels
+    int cu_count;
+    // workspace: depth pyramid, env mip chain, per-sample hit codes of the
+    // hierarchical path (when the caller asks for none) and its tile counter
+    float4* hiz;
+    int64_t hiz_cap;    // float4 texels
     float4* mips;
     int64_t mips_cap;   // float4 texels
+    int32_t* codes;
+    int64_t codes_cap;  // int32
+    int* counter;
 };
 
 namespace {
@@ -101,10 +106,20 @@ int ssr_ctx_create(int device, ssr_ctx** out) {
     ssr_ctx* c = new (std::nothrow) ssr_ctx;
     if (!c) return SSR_E_NOMEM;
     c->device = device;
+    c->cu_count = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 1;
     c->hiz = nullptr;
     c->hiz_cap = 0;
     c->mips = nullptr;
     c->mips_cap = 0;
+    c->codes = nullptr;
+    c->codes_cap = 0;
+    c->counter = nullptr;
+    if (hipSetDevice(device) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&c->counter), 256) != hipSuccess) {
+        (void)hipGetLastError();
+        delete c;
+        return SSR_E_NOMEM;
+    }
     *out = c;
     return SSR_OK;
 }
@@ -115,6 +130,8 @@ void ssr_ctx_destroy(ssr_ctx* ctx) {
         (void)hipDeviceSynchronize();
         if (ctx->hiz) (void)hipFree(ctx->hiz);
         if (ctx->mips) (void)hipFree(ctx->mips);
+        if (ctx->codes) (void)hipFree(ctx->codes);
+        if (ctx->counter) (void)hipFree(ctx->counter);
     }
     delete ctx;
 }
@@ -136,7 +153,7 @@ int ssr_env_build_mips(const float* rgb, int32_t width, int32_t height, float* m
 int64_t ssr_hiz_floats(int32_t width, int32_t height) {
     ssr::HizLayout lay;
     if (!ssr::make_hiz_layout(width, height, &lay)) return 0;
-    return 2 * lay.total;
+    return 4 * lay.total;
 }
 
 int ssr_hiz_build(const float* depth, int32_t width, int32_t height, float thickness,
@@ -144,7 +161,7 @@ int ssr_hiz_build(const float* depth, int32_t width, int32_t height, float thick
     ssr::HizLayout lay;
     if (!depth || !pyramid || !ssr::make_hiz_layout(width, height, &lay)) return SSR_E_ARG;
     if (!(thickness >= 0.0f) || !finite_f(thickness)) return SSR_E_ARG;
-    return hip_status(ssr::launch_hiz(depth, lay, thickness, reinterpret_cast<float2*>(pyramid),
+    return hip_status(ssr::launch_hiz(depth, lay, thickness, reinterpret_cast<float4*>(pyramid),
                                       static_cast<hipStream_t>(stream)));
 }
 
@@ -184,13 +201,20 @@ int ssr_shade(ssr_ctx* ctx, const ssr_camera* cam, const ssr_gbuffer* g, const s
         if (st != SSR_OK) return st;
         mips = ctx->mips;
     }
-    const float2* hiz = reinterpret_cast<const float2*>(g->hiz);
+    const float4* hiz = reinterpret_cast<const float4*>(g->hiz);
     if (p->march == SSR_MARCH_HIZ && !hiz) {
         st = ensure(&ctx->hiz, &ctx->hiz_cap, hiz_lay.total);
         if (st != SSR_OK) return st;
         st = hip_status(ssr::launch_hiz(g->depth, hiz_lay, p->thickness, ctx->hiz, s));
         if (st != SSR_OK) return st;
         hiz = ctx->hiz;
+    }
+    int32_t* codes = out_hits;
+    if (p->march == SSR_MARCH_HIZ && !codes) {
+        const int64_t n = static_cast<int64_t>(cam->width) * cam->height * p->spp;
+        st = ensure(&ctx->codes, &ctx->codes_cap, n);
+        if (st != SSR_OK) return st;
+        codes = ctx->codes;
     }
 
     ssr::ShadeArgs a;
@@ -234,7 +258,9 @@ int ssr_shade(ssr_ctx* ctx, const ssr_camera* cam, const ssr_gbuffer* g, const s
     a.out = out_rgb;
     a.hits = out_hits;
     a.steps = out_steps;
-    return hip_status(ssr::launch_shade(a, g->dtype, p->march, s));
+    a.codes = codes;
+    a.tile_counter = ctx->counter;
+    return hip_status(ssr::launch_shade(a, g->dtype, p->march, ctx->cu_count, s));
 }
 
 }  // extern "C"

@@ -30,10 +30,12 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
             k0 += Philox::kWeyl0;
             k1 += Philox::kWeyl1;
         }
-        const uint32_t lo0 = Philox::kMul0 * c.x;
-        const uint32_t hi0 = __umulhi(Philox::kMul0, c.x);
-        const uint32_t lo1 = Philox::kMul1 * c.z;
-        const uint32_t hi1 = __umulhi(Philox::kMul1, c.z);
+        // full 64-bit products: one v_mad_u64_u32 each instead of a
+        // separate low and high multiply
+        const uint64_t p0 = static_cast<uint64_t>(Philox::kMul0) * c.x;
+        const uint64_t p1 = static_cast<uint64_t>(Philox::kMul1) * c.z;
+        const uint32_t lo0 = static_cast<uint32_t>(p0), hi0 = static_cast<uint32_t>(p0 >> 32);
+        const uint32_t lo1 = static_cast<uint32_t>(p1), hi1 = static_cast<uint32_t>(p1 >> 32);
         c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
     }
     return c;

@@ -21,13 +21,14 @@ struct EnvLayout {
     int64_t total;               // float4 texels
 };
 
-// Min-max depth pyramid: levels 0..top, each texel a float2 (min, max) of the
-// depths it covers, row-major, level after level.
+// Depth pyramid: levels 0..top, each texel a float4: its own pair
+// (1/min D, 1/max(D + thickness)) over the pixels it covers, then its
+// parent's pair (the top texel repeats its own), row-major, level after level.
 struct HizLayout {
     int levels;               // top + 1
     int w[kMaxLevels], h[kMaxLevels];
-    int offset[kMaxLevels];   // in float2 texels
-    int64_t total;            // float2 texels
+    int offset[kMaxLevels];   // in texels
+    int64_t total;            // texels
 };
 
 bool make_env_layout(int w, int h, EnvLayout* out);
@@ -45,7 +46,7 @@ struct ShadeArgs {
     const void* radiance;
     const float4* env;        // mip chain (EnvLayout)
     EnvLayout env_lay;
-    const float2* hiz;        // slab pyramid (HizLayout): (1/min D, 1/max(D + thickness))
+    const float4* hiz;        // depth pyramid (HizLayout)
     HizLayout hiz_lay;
     int spp, max_steps, linear_samples;
     float step_len, max_dist, thickness;
@@ -53,13 +54,16 @@ struct ShadeArgs {
     float* out;
     int32_t* hits;
     int32_t* steps;
+    int32_t* codes;           // hierarchical path: per-sample hit codes [H][W][spp]
+    int* tile_counter;        // hierarchical path: next tile of the trace kernel
 };
 
 hipError_t launch_env_mips(const float* rgb, const EnvLayout& lay, float4* mips,
                            hipStream_t stream);
-hipError_t launch_hiz(const float* depth, const HizLayout& lay, float thickness, float2* pyramid,
+hipError_t launch_hiz(const float* depth, const HizLayout& lay, float thickness, float4* pyramid,
                       hipStream_t stream);
-hipError_t launch_shade(const ShadeArgs& args, int dtype, int march, hipStream_t stream);
+hipError_t launch_shade(const ShadeArgs& args, int dtype, int march, int cu_count,
+                        hipStream_t stream);
 hipError_t launch_philox(const uint32_t* ctr, const uint32_t* key, int64_t n, uint32_t* out,
                          hipStream_t stream);
 

@@ -47,7 +47,8 @@ bool make_hiz_layout(int w, int h, HizLayout* out) {
     }
     out->levels = L + 1;
     out->total = off;
-    return true;
+    // the march addresses texels with 32-bit byte offsets
+    return off * static_cast<int64_t>(sizeof(float4)) <= (int64_t(1) << 32) - 16;
 }
 
 // ---------------------------------------------------------------- env mips --
@@ -99,6 +100,8 @@ hipError_t launch_env_mips(const float* rgb, const EnvLayout& lay, float4* mips,
 //
 // Pass 2: the levels above 6.  When level 6 fits in LDS, one workgroup does
 // them all there; otherwise one launch per level from global memory.
+//
+// Texels are stored as (own pair, parent's pair), see put_level.
 
 constexpr int kTile = 64;
 constexpr int kTileLevels = 6;
@@ -108,26 +111,57 @@ __device__ __forceinline__ float2 mm(float2 a, float2 b) {
     return make_float2(fmaxf(a.x, b.x), fminf(a.y, b.y));
 }
 
+// A texel is stored as float4: its own pair, then its parent's pair (the top
+// texel: its own again), so that the march reads a cell and its parent with
+// one load.  Each pass writes the own pairs of the texels it computes and the
+// parent pairs of their children; the pass that computes the top level also
+// completes the top texel.
+__device__ __forceinline__ void put(float4* __restrict__ pyr, int64_t i, float2 v) {
+    *reinterpret_cast<float2*>(pyr + i) = v;
+}
+__device__ __forceinline__ void put_parent(float4* __restrict__ pyr, int64_t i, float2 v) {
+    reinterpret_cast<float2*>(pyr + i)[1] = v;
+}
+__device__ __forceinline__ float2 own(const float4* __restrict__ p, int64_t i) {
+    const float4 t = p[i];
+    return make_float2(t.x, t.y);
+}
+
+// Texel (x, y) of level L >= 1 holds v: write it, hand v to its children as
+// their parent, and complete it if it is the top texel.
+__device__ __forceinline__ void put_level(float4* __restrict__ pyr, const HizLayout& lay, int L,
+                                          int x, int y, float2 v) {
+    const int64_t at = lay.offset[L] + static_cast<int64_t>(y) * lay.w[L] + x;
+    put(pyr, at, v);
+    if (L == lay.levels - 1) put_parent(pyr, at, v);
+    const int cw = lay.w[L - 1], ch = lay.h[L - 1];
+#pragma unroll
+    for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+        for (int dx = 0; dx < 2; ++dx)
+            if (2 * x + dx < cw && 2 * y + dy < ch)
+                put_parent(pyr, lay.offset[L - 1] + static_cast<int64_t>(2 * y + dy) * cw + 2 * x + dx, v);
+}
+
 __global__ __launch_bounds__(256) void hiz_tile_kernel(const float* __restrict__ depth,
-                                                       float2* __restrict__ pyr, HizLayout lay,
+                                                       float4* __restrict__ pyr, HizLayout lay,
                                                        float thickness, int tile_levels) {
     __shared__ float2 lds[2][16 * 16];
     const int W = lay.w[0], H = lay.h[0];
+    const int top = lay.levels - 1;
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
     const int x0 = blockIdx.x * kTile + tx * 4;
     const int y0 = blockIdx.y * kTile + ty * 4;
     float2 p[4][4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        const int y = y0 + r;
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-            const int x = x0 + c;
+            const int x = x0 + c, y = y0 + r;
             const bool in = x < W && y < H;
             const float D = in ? depth[static_cast<int64_t>(y) * W + x] : 1.0f;
             p[r][c] = in ? make_float2(1.0f / D, 1.0f / (D + thickness))
                          : make_float2(-INFINITY, INFINITY);
-            if (in) pyr[static_cast<int64_t>(y) * W + x] = p[r][c];
         }
     }
     // level 1: 2 x 2 texels per thread
@@ -138,6 +172,18 @@ __global__ __launch_bounds__(256) void hiz_tile_kernel(const float* __restrict__
         for (int a = 0; a < 2; ++a)
             m1[b][a] = mm(mm(p[2 * b][2 * a], p[2 * b][2 * a + 1]),
                           mm(p[2 * b + 1][2 * a], p[2 * b + 1][2 * a + 1]));
+    const float2 m2 = mm(mm(m1[0][0], m1[0][1]), mm(m1[1][0], m1[1][1]));
+    // levels 0 and 1 with their parents (levels 1 and 2) from registers
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int x = x0 + c, y = y0 + r;
+            if (x < W && y < H) {
+                const float2 par = top >= 1 ? m1[r >> 1][c >> 1] : p[r][c];
+                pyr[static_cast<int64_t>(y) * W + x] = make_float4(p[r][c].x, p[r][c].y, par.x, par.y);
+            }
+        }
     if (tile_levels < 1) return;
     {
         const int lx = x0 / 2, ly = y0 / 2;
@@ -145,14 +191,21 @@ __global__ __launch_bounds__(256) void hiz_tile_kernel(const float* __restrict__
         for (int b = 0; b < 2; ++b)
 #pragma unroll
             for (int a = 0; a < 2; ++a)
-                if (lx + a < lay.w[1] && ly + b < lay.h[1])
-                    pyr[lay.offset[1] + (ly + b) * lay.w[1] + lx + a] = m1[b][a];
+                if (lx + a < lay.w[1] && ly + b < lay.h[1]) {
+                    const float2 par = top >= 2 ? m2 : m1[b][a];
+                    pyr[lay.offset[1] + (ly + b) * lay.w[1] + lx + a] =
+                        make_float4(m1[b][a].x, m1[b][a].y, par.x, par.y);
+                }
     }
     if (tile_levels < 2) return;
-    const float2 m2 = mm(mm(m1[0][0], m1[0][1]), mm(m1[1][0], m1[1][1]));
     {
+        // level 2: its parent comes from the LDS pass below (or it is the top)
         const int lx = x0 / 4, ly = y0 / 4;
-        if (lx < lay.w[2] && ly < lay.h[2]) pyr[lay.offset[2] + ly * lay.w[2] + lx] = m2;
+        if (lx < lay.w[2] && ly < lay.h[2]) {
+            const int64_t at = lay.offset[2] + ly * lay.w[2] + lx;
+            put(pyr, at, m2);
+            if (top == 2) put_parent(pyr, at, m2);
+        }
     }
     lds[0][ty * 16 + tx] = m2;
     int n = 16;  // current level's tile width in texels
@@ -167,49 +220,52 @@ __global__ __launch_bounds__(256) void hiz_tile_kernel(const float* __restrict__
                                 mm(s[(2 * b + 1) * n + 2 * a], s[(2 * b + 1) * n + 2 * a + 1]));
             lds[cur ^ 1][b * m + a] = v;
             const int lx = blockIdx.x * (kTile >> L) + a, ly = blockIdx.y * (kTile >> L) + b;
-            if (lx < lay.w[L] && ly < lay.h[L]) pyr[lay.offset[L] + ly * lay.w[L] + lx] = v;
+            if (lx < lay.w[L] && ly < lay.h[L]) put_level(pyr, lay, L, lx, ly, v);
         }
         cur ^= 1;
         n = m;
     }
 }
 
-__device__ __forceinline__ float2 children(const float2* __restrict__ src, int sw, int sh, int x,
-                                           int y) {
-    float2 v = src[(2 * y) * sw + 2 * x];
-    if (2 * x + 1 < sw) v = mm(v, src[(2 * y) * sw + 2 * x + 1]);
+template <typename Get>
+__device__ __forceinline__ float2 children(Get get, int sw, int sh, int x, int y) {
+    float2 v = get((2 * y) * sw + 2 * x);
+    if (2 * x + 1 < sw) v = mm(v, get((2 * y) * sw + 2 * x + 1));
     if (2 * y + 1 < sh) {
-        v = mm(v, src[(2 * y + 1) * sw + 2 * x]);
-        if (2 * x + 1 < sw) v = mm(v, src[(2 * y + 1) * sw + 2 * x + 1]);
+        v = mm(v, get((2 * y + 1) * sw + 2 * x));
+        if (2 * x + 1 < sw) v = mm(v, get((2 * y + 1) * sw + 2 * x + 1));
     }
     return v;
 }
 
-// One level from the level below it (global memory), for any level >= 1.
-__global__ void hiz_level_kernel(const float2* __restrict__ src, int sw, int sh,
-                                 float2* __restrict__ dst, int dw, int dh) {
+// One level L >= 1 from the level below it (global memory).
+__global__ void hiz_level_kernel(float4* __restrict__ pyr, HizLayout lay, int L) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= dw * dh) return;
-    dst[i] = children(src, sw, sh, i % dw, i / dw);
+    const int dw = lay.w[L];
+    if (i >= dw * lay.h[L]) return;
+    const float4* src = pyr + lay.offset[L - 1];
+    const float2 v = children([&](int k) { return own(src, k); }, lay.w[L - 1], lay.h[L - 1], i % dw,
+                              i / dw);
+    put_level(pyr, lay, L, i % dw, i / dw, v);
 }
 
 constexpr int kTopLdsTexels = 8192;  // 64 KB of LDS for the levels above the tile pass
 
 // All levels from `first` up, in one workgroup, ping-ponging through LDS.
-__global__ __launch_bounds__(1024) void hiz_top_kernel(float2* __restrict__ pyr, HizLayout lay,
+__global__ __launch_bounds__(1024) void hiz_top_kernel(float4* __restrict__ pyr, HizLayout lay,
                                                        int first) {
     extern __shared__ float2 lds2[];
     const int sw0 = lay.w[first - 1], sh0 = lay.h[first - 1];
     float2* a = lds2;
     float2* b = lds2 + sw0 * sh0;
-    for (int i = threadIdx.x; i < sw0 * sh0; i += blockDim.x) a[i] = pyr[lay.offset[first - 1] + i];
+    for (int i = threadIdx.x; i < sw0 * sh0; i += blockDim.x) a[i] = own(pyr, lay.offset[first - 1] + i);
     for (int L = first; L < lay.levels; ++L) {
         __syncthreads();
         const int sw = lay.w[L - 1], sh = lay.h[L - 1], dw = lay.w[L], dh = lay.h[L];
         for (int i = threadIdx.x; i < dw * dh; i += blockDim.x) {
-            const float2 v = children(a, sw, sh, i % dw, i / dw);
+            const float2 v = children([&](int k) { return a[k]; }, sw, sh, i % dw, i / dw);
             b[i] = v;
-            pyr[lay.offset[L] + i] = v;
+            put_level(pyr, lay, L, i % dw, i / dw, v);
         }
         float2* t = a;
         a = b;
@@ -217,7 +273,7 @@ __global__ __launch_bounds__(1024) void hiz_top_kernel(float2* __restrict__ pyr,
     }
 }
 
-hipError_t launch_hiz(const float* depth, const HizLayout& lay, float thickness, float2* pyramid,
+hipError_t launch_hiz(const float* depth, const HizLayout& lay, float thickness, float4* pyramid,
                       hipStream_t stream) {
     const int top = lay.levels - 1;
     const int tile_levels = top < kTileLevels ? top : kTileLevels;
@@ -235,8 +291,7 @@ hipError_t launch_hiz(const float* depth, const HizLayout& lay, float thickness,
             for (int L = first; L <= top; ++L) {
                 const int n = lay.w[L] * lay.h[L];
                 hipLaunchKernelGGL(hiz_level_kernel, dim3((n + 255) / 256), dim3(256), 0, stream,
-                                   pyramid + lay.offset[L - 1], lay.w[L - 1], lay.h[L - 1],
-                                   pyramid + lay.offset[L], lay.w[L], lay.h[L]);
+                                   pyramid, lay, L);
             }
         }
     }

@@ -143,8 +143,7 @@ __device__ __forceinline__ HizSegment hiz_segment(const ShadeArgs& a, int i, int
 // inv = +inf: its crossings are then NaN, which fminf ignores, and the far
 // screen edge is never reached.
 struct HizRay {
-    int i, j;             // origin pixel
-    float P0x, P0y;       // its centre
+    float P0x, P0y;       // centre of the origin pixel
     float dPx, dPy;
     float inv_dx, inv_dy; // 1 / dP
     float bx, by;         // -P0 / dP
@@ -159,8 +158,6 @@ struct HizRay {
 
 __device__ __forceinline__ void hiz_start(const ShadeArgs& a, HizRay& r, int i, int j, float dPx,
                                           float dPy, float iz0, float diz) {
-    r.i = i;
-    r.j = j;
     r.P0x = static_cast<float>(i) + 0.5f;
     r.P0y = static_cast<float>(j) + 0.5f;
     r.dPx = dPx;
@@ -189,22 +186,23 @@ __device__ __forceinline__ void hiz_start(const ShadeArgs& a, HizRay& r, int i, 
 // One iteration, branch-free.  Returns true when the ray is finished; then
 // `hit` tells a hit at (ix, iy) from leaving the screen or the segment (or
 // the iteration cap, which the caller tells by r.it).  `lvl[L]` holds
-// (offset, width) of level L and of its parent; the top level's parent is the
-// top texel again with width 0, so the look-ahead needs no special case there
-// (skipping it means leaving the screen, as skipping the top cell does).
-__device__ __forceinline__ bool hiz_step(const ShadeArgs& a, const int4* lvl, HizRay& r, bool& hit,
+// (offset, width) of level L.  A texel holds the cell's pair and its
+// parent's, so one 16 B load serves both; the top texel is its own parent,
+// so the look-ahead needs no special case there (skipping it means leaving
+// the screen, as skipping the top cell does).
+__device__ __forceinline__ bool hiz_step(const ShadeArgs& a, const int2* lvl, HizRay& r, bool& hit,
                                          bool& leave) {
     const int L = r.L, Lp = L + 1;
     ++r.it;
-    const int4 lv = lvl[L];
+    const int2 lv = lvl[L];
     const int cx = r.ix >> L, cy = r.iy >> L, px = r.ix >> Lp, py = r.iy >> Lp;
     // 32-bit byte offsets from a base held in SGPRs (the pyramid is < 4 GiB;
     // row index and width are below 2^14, so the 24-bit multiply is exact)
     const char* base = reinterpret_cast<const char*>(a.hiz);
-    const unsigned oc = (lv.x + __umul24(cy, lv.y) + cx) << 3;
-    const unsigned op = (lv.z + __umul24(py, lv.w) + px) << 3;
-    const float2 zc = *reinterpret_cast<const float2*>(base + oc);  // (1/min D, 1/max(D + th))
-    const float2 zp = *reinterpret_cast<const float2*>(base + op);
+    const unsigned oc = (lv.x + __umul24(cy, lv.y) + cx) << 4;
+    // (1/min D, 1/max(D + th)) of the cell, then of its parent
+    const float4 z = *reinterpret_cast<const float4*>(base + oc);
+    const float2 zc = make_float2(z.x, z.y), zp = make_float2(z.z, z.w);
     // the boundaries the segment leaves the cell and the parent through
     const int ecx = (cx + r.xp) << L, ecy = (cy + r.yp) << L;
     const int epx = (px + r.xp) << Lp, epy = (py + r.yp) << Lp;
@@ -224,7 +222,9 @@ __device__ __forceinline__ bool hiz_step(const ShadeArgs& a, const int4* lvl, Hi
     // outcomes: skip the parent / skip the cell / go down / level-0 pixel
     const bool stay = !up & !skip_c;
     const bool at0 = L == 0;
-    const bool test = stay & at0 & ((r.ix != r.i) | (r.iy != r.j));
+    // (the segment starts in the origin pixel, at s = 0, and every move
+    // crosses into another pixel, so it is outside the origin pixel once s > 0)
+    const bool test = stay & at0 & (r.s > 0.0f);
     hit = test & (r.armed | (r.iz_in > zc.x));
     const bool move = !hit & (!stay | at0);
     // the cell the segment moves across
@@ -418,23 +418,33 @@ __global__ __launch_bounds__(256) void shade_linear_kernel(const ShadeArgs a) {
     write_out(a, q, direct_term(a, P, i, j), sum);
 }
 
-// ------------------------------------------------ hierarchical-march kernel --
+// ---------------------------------------------------- hierarchical path --
 //
-// One wave64 per 8 x 8 pixel tile, samples in chunks of kChunk per pixel.
-// For each chunk:
-//   1. generate: each lane draws its pixel's samples of the chunk; the rays
-//      that need marching go to an LDS queue, compacted (ballot + popcount);
-//      the others get their hit code at once;
-//   2. march: the lanes take rays from the queue, any lane any ray, and a
-//      lane that finishes takes the next one.  Idle lanes are refilled
-//      together once kRefillMin of them wait (or the queue is shorter), so
-//      the wave pays for the average ray length instead of the longest ray
-//      of every sample;
-//   3. finish: each lane draws its samples again, reads their hit codes and
-//      accumulates weight x radiance in sample order (Kahan), so the result
-//      does not depend on which lane marched which ray.
-#ifndef SSR_CHUNK
-#define SSR_CHUNK 4
+// Two kernels.  The trace kernel marches every ray of the frame and writes
+// each sample's hit code; the resolve kernel then shades each pixel from the
+// codes of its samples.
+//
+// Trace: persistent wave64s take 8 x 8 pixel tiles from a global counter.
+// The rays flow through a per-wave pool instead of being marched in
+// lockstep:
+//   * generate: every lane draws its pixel's sample k of the current tile
+//     (a few k at a time); the rays that need marching go to an LDS ring
+//     queue, compacted (ballot + popcount); the others get their hit code at
+//     once.  When a tile's samples are all drawn the wave takes the next tile;
+//   * march: lanes take rays from the queue, any lane any ray, and a lane
+//     whose ray ends takes the next one.  Idle lanes are refilled together
+//     once kRefillMin of them wait (or the queue is shorter).
+// New rays are drawn while older ones are still marching, across tile
+// boundaries, so the lanes stay busy until the frame runs out of tiles.
+//
+// Resolve: one thread per pixel draws its samples again and accumulates
+// weight x radiance in sample order (Kahan), reading each sample's hit code,
+// so the result does not depend on which lane marched which ray.
+#ifndef SSR_GEN_BATCH
+#define SSR_GEN_BATCH 2
+#endif
+#ifndef SSR_QUEUE_LOW
+#define SSR_QUEUE_LOW 64
 #endif
 #ifndef SSR_REFILL_MIN
 #define SSR_REFILL_MIN 8
@@ -442,134 +452,159 @@ __global__ __launch_bounds__(256) void shade_linear_kernel(const ShadeArgs a) {
 #ifndef SSR_WAVES_PER_EU
 #define SSR_WAVES_PER_EU 5
 #endif
-constexpr int kChunk = SSR_CHUNK;
+constexpr int kGenBatch = SSR_GEN_BATCH;   // sample indices drawn at once
+constexpr int kQueueLow = SSR_QUEUE_LOW;   // draw when fewer rays than this wait
 constexpr int kRefillMin = SSR_REFILL_MIN;
+constexpr int kTraceWavesPerEU = SSR_WAVES_PER_EU;
+// the queue never holds more than kQueueLow - 1 + kGenBatch * 64 rays
+constexpr int kQueueCap = 256;
+static_assert(kQueueLow - 1 + kGenBatch * 64 <= kQueueCap, "ray queue too small");
+
+__global__ void reset_counter_kernel(int* counter) { *counter = 0; }
 
 template <int DT>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(SSR_WAVES_PER_EU, 8)))
-void shade_hiz_kernel(const ShadeArgs a) {
-    __shared__ int4 lvl[kMaxLevels];
-    __shared__ float4 q_seg[kChunk * 64];   // queued rays: (dPx, dPy, iz0, diz)
-    __shared__ int q_slot[kChunk * 64];     //   and their slot k * 64 + lane
-    __shared__ int r_code[kChunk * 64];     // per (sample of the chunk, lane)
-    __shared__ int r_iters[kChunk * 64];
+void trace_hiz_kernel(const ShadeArgs a) {
+    __shared__ int2 lvl[kMaxLevels];
+    __shared__ float4 q_seg[kQueueCap];     // queued rays: (dPx, dPy, iz0, diz)
+    __shared__ int2 q_ray[kQueueCap];       //   and (i | j << 16, sample index)
     const int lane = threadIdx.x;
     {
-        const int nl = a.hiz_lay.levels;
-        if (lane < nl) {
-            const bool top = lane == nl - 1;
-            lvl[lane] = make_int4(a.hiz_lay.offset[lane], a.hiz_lay.w[lane],
-                                  a.hiz_lay.offset[top ? lane : lane + 1],
-                                  top ? 0 : a.hiz_lay.w[lane + 1]);
+        // levels past the top (never reached) alias the top texel
+        const int top = a.hiz_lay.levels - 1;
+        if (lane < kMaxLevels) {
+            const int L = min(lane, top);
+            lvl[lane] = make_int2(a.hiz_lay.offset[L], lane < top ? a.hiz_lay.w[L] : 0);
         }
     }
     const int tiles_x = (a.W + 7) / 8;
-    const int ti = (blockIdx.x % tiles_x) * 8, tj = (blockIdx.x / tiles_x) * 8;
-    const int i = ti + (lane & 7), j = tj + (lane >> 3);
-    const bool inb = i < a.W && j < a.H;
-    const int64_t q = inb ? static_cast<int64_t>(j) * a.W + i : 0;
+    const int n_tiles = tiles_x * ((a.H + 7) / 8);
     const int S = a.spp;
     const unsigned long long below = (1ull << lane) - 1ull;
-    float sum[3] = {0.0f, 0.0f, 0.0f}, cmp[3] = {0.0f, 0.0f, 0.0f};
+    auto next_tile = [&]() {
+        int t = 0;
+        if (lane == 0) t = atomicAdd(a.tile_counter, 1);
+        return __shfl(t, 0);
+    };
     __syncthreads();
 
-    for (int s0 = 0; s0 < S; s0 += kChunk) {
-        const int nch = min(kChunk, S - s0);
-        // 1. generate.  The per-pixel setup is recomputed in each phase rather
-        // than kept live through the march (the compiler barrier stops it
-        // being hoisted out of the chunk loop).
-        int qn = 0;
-        {
+    int tile = next_tile();     // tile being drawn (n_tiles or more: none left)
+    int kk = 0;                 // its next sample index
+    int qh = 0, qt = 0;         // queue head and tail (monotone; slots modulo kQueueCap)
+    HizRay r;
+    int32_t* dst = nullptr;     // where the marching ray's hit code goes
+    bool active = false;
+    for (;;) {
+        // draw more rays while the queue runs low
+        if (tile < n_tiles && qt - qh < kQueueLow) {
             asm volatile("" ::: "memory");
+            const int i = (tile % tiles_x) * 8 + (lane & 7), j = (tile / tiles_x) * 8 + (lane >> 3);
+            const bool inb = i < a.W && j < a.H;
+            const int64_t q = inb ? static_cast<int64_t>(j) * a.W + i : 0;
+            const int g = min(kGenBatch, S - kk);
             const Pixel P = setup_pixel<DT>(a, i, j, q);
             const bool trace = inb && P.trace;
             const int fill = fill_code(a, P);
 #pragma unroll 1
-            for (int k = 0; k < nch; ++k) {
+            for (int k = kk; k < kk + g; ++k) {
                 int code = fill;
                 bool queue = false;
-                HizSegment g;
+                HizSegment sg;
                 if (trace) {
-                    const SampleDir d = sample_dir(a, P, q, s0 + k);
+                    const SampleDir d = sample_dir(a, P, q, k);
                     if (d.cos_nl > 0.0f) {
-                        g = hiz_segment(a, i, j, v3(P.X0, P.Y0, P.D), world_to_view(a, d.l));
-                        queue = g.valid;
+                        sg = hiz_segment(a, i, j, v3(P.X0, P.Y0, P.D), world_to_view(a, d.l));
+                        queue = sg.valid;
                         code = SSR_HIT_OFFSCREEN;
                     }
                 }
                 const unsigned long long m = __ballot(queue);
                 if (queue) {
-                    const int pos = qn + __popcll(m & below);
-                    q_seg[pos] = make_float4(g.dPx, g.dPy, g.iz0, g.diz);
-                    q_slot[pos] = k * 64 + lane;
-                } else {
-                    r_code[k * 64 + lane] = code;
-                    r_iters[k * 64 + lane] = 0;
+                    const int pos = (qt + __popcll(m & below)) & (kQueueCap - 1);
+                    q_seg[pos] = make_float4(sg.dPx, sg.dPy, sg.iz0, sg.diz);
+                    q_ray[pos] = make_int2(i | (j << 16), k);
+                } else if (inb) {
+                    a.codes[q * S + k] = code;
+                    if (a.steps) a.steps[q * S + k] = 0;
                 }
-                qn += __popcll(m);
+                qt += __popcll(m);
             }
-        }
-        __syncthreads();
-        // 2. march the queue
-        {
-            HizRay r;
-            int slot = 0;
-            bool active = false;
-            int qh = 0;
-            for (;;) {
-                const unsigned long long idle = __ballot(!active);
-                const int nidle = __popcll(idle);
-                const int rem = qn - qh;
-                if (rem > 0 && nidle >= min(kRefillMin, rem)) {
-                    const int rank = __popcll(idle & below);
-                    if (!active && rank < rem) {
-                        const float4 gq = q_seg[qh + rank];
-                        slot = q_slot[qh + rank];
-                        const int ln = slot & 63;
-                        hiz_start(a, r, ti + (ln & 7), tj + (ln >> 3), gq.x, gq.y, gq.z, gq.w);
-                        active = true;
-                    }
-                    qh += min(nidle, rem);
-                }
-                if (!__any(active)) break;
-                if (active) {
-                    bool hit, leave;
-                    if (hiz_step(a, lvl, r, hit, leave)) {
-                        r_code[slot] = hit ? r.iy * a.W + r.ix
-                                           : (leave ? SSR_HIT_OFFSCREEN : SSR_HIT_CAP);
-                        r_iters[slot] = r.it;
-                        active = false;
-                    }
-                }
+            kk += g;
+            if (kk == S) {
+                tile = next_tile();
+                kk = 0;
             }
+            __builtin_amdgcn_wave_barrier();
+            continue;
         }
-        __syncthreads();
-        // 3. finish
-        {
-            asm volatile("" ::: "memory");
-            const Pixel P = setup_pixel<DT>(a, i, j, q);
-#pragma unroll 1
-            for (int k = 0; k < nch; ++k) {
-                const int code = r_code[k * 64 + lane];
-                if (inb && P.trace &&
-                    (code >= 0 || code == SSR_HIT_OFFSCREEN || code == SSR_HIT_CAP)) {
-                    const SampleDir d = sample_dir(a, P, q, s0 + k);
-                    accumulate<DT>(a, P, d, code, sum, cmp);
+        // march until the queue runs low again (while tiles remain) or drains
+        for (;;) {
+            const unsigned long long idle = __ballot(!active);
+            const int nidle = __popcll(idle);
+            const int rem = qt - qh;
+            if (rem > 0 && nidle >= min(kRefillMin, rem)) {
+                const int rank = __popcll(idle & below);
+                if (!active && rank < rem) {
+                    const int pos = (qh + rank) & (kQueueCap - 1);
+                    const float4 gq = q_seg[pos];
+                    const int2 ray = q_ray[pos];
+                    const int ri = ray.x & 0xFFFF, rj = ray.x >> 16;
+                    hiz_start(a, r, ri, rj, gq.x, gq.y, gq.z, gq.w);
+                    dst = a.codes + (static_cast<int64_t>(rj) * a.W + ri) * S + ray.y;
+                    active = true;
                 }
-                if (inb) {
-                    if (a.hits) a.hits[q * S + s0 + k] = code;
-                    if (a.steps) a.steps[q * S + s0 + k] = r_iters[k * 64 + lane];
+                qh += min(nidle, rem);
+            }
+            if (!__any(active)) break;
+            if (active) {
+                bool hit, leave;
+                if (hiz_step(a, lvl, r, hit, leave)) {
+                    *dst = hit ? r.iy * a.W + r.ix : (leave ? SSR_HIT_OFFSCREEN : SSR_HIT_CAP);
+                    if (a.steps) a.steps[dst - a.codes] = r.it;
+                    active = false;
                 }
             }
+            if (tile < n_tiles && qt - qh < kQueueLow) break;
         }
-        __syncthreads();
+        __builtin_amdgcn_wave_barrier();
+        if (tile >= n_tiles && qt == qh && !__any(active)) break;
     }
-    if (!inb) return;
+}
+
+// Workgroups of 256 threads shade 16 x 16 pixel tiles, one thread per pixel.
+template <int DT>
+__global__ __launch_bounds__(256) void resolve_kernel(const ShadeArgs a) {
+    const int tiles_x = (a.W + 15) / 16;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int i = (blockIdx.x % tiles_x) * 16 + (wave & 1) * 8 + (lane & 7);
+    const int j = (blockIdx.x / tiles_x) * 16 + (wave >> 1) * 8 + (lane >> 3);
+    if (i >= a.W || j >= a.H) return;
+    const int64_t q = static_cast<int64_t>(j) * a.W + i;
+    const int S = a.spp;
     const Pixel P = setup_pixel<DT>(a, i, j, q);
+    float sum[3] = {0.0f, 0.0f, 0.0f}, cmp[3] = {0.0f, 0.0f, 0.0f};
+    if (P.trace) {
+        const int32_t* codes = a.codes + q * S;
+#pragma unroll 1
+        for (int s = 0; s < S; ++s) {
+            const int code = codes[s];
+            if (code >= 0 || code == SSR_HIT_OFFSCREEN || code == SSR_HIT_CAP) {
+                const SampleDir d = sample_dir(a, P, q, s);
+                accumulate<DT>(a, P, d, code, sum, cmp);
+            }
+        }
+    }
     write_out(a, q, direct_term(a, P, i, j), sum);
 }
 
-hipError_t launch_shade(const ShadeArgs& args, int dtype, int march, hipStream_t stream) {
+int trace_grid(int cu_count, int W, int H) {
+    const int n_tiles = ((W + 7) / 8) * ((H + 7) / 8);
+    const int resident = cu_count * 4 * kTraceWavesPerEU;
+    return n_tiles < resident ? n_tiles : resident;
+}
+
+hipError_t launch_shade(const ShadeArgs& args, int dtype, int march, int cu_count,
+                        hipStream_t stream) {
     if (march == 0) {
         const dim3 grid(((args.W + 15) / 16) * ((args.H + 15) / 16));
 #define SSR_LAUNCH(DT) \
@@ -578,15 +613,20 @@ hipError_t launch_shade(const ShadeArgs& args, int dtype, int march, hipStream_t
         else if (dtype == 1) SSR_LAUNCH(1);
         else SSR_LAUNCH(2);
 #undef SSR_LAUNCH
-    } else {
-        const dim3 grid(((args.W + 7) / 8) * ((args.H + 7) / 8));
-#define SSR_LAUNCH(DT) \
-    hipLaunchKernelGGL((shade_hiz_kernel<DT>), grid, dim3(64), 0, stream, args)
-        if (dtype == 0) SSR_LAUNCH(0);
-        else if (dtype == 1) SSR_LAUNCH(1);
-        else SSR_LAUNCH(2);
-#undef SSR_LAUNCH
+        return hipGetLastError();
     }
+    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, stream, args.tile_counter);
+    const dim3 tgrid(trace_grid(cu_count, args.W, args.H));
+    const dim3 rgrid(((args.W + 15) / 16) * ((args.H + 15) / 16));
+#define SSR_LAUNCH(DT)                                                                          \
+    do {                                                                                        \
+        hipLaunchKernelGGL((trace_hiz_kernel<DT>), tgrid, dim3(64), 0, stream, args);           \
+        hipLaunchKernelGGL((resolve_kernel<DT>), rgrid, dim3(256), 0, stream, args);            \
+    } while (0)
+    if (dtype == 0) SSR_LAUNCH(0);
+    else if (dtype == 1) SSR_LAUNCH(1);
+    else SSR_LAUNCH(2);
+#undef SSR_LAUNCH
     return hipGetLastError();
 }
 

@@ -80,15 +80,18 @@ def test_sizes_and_status_strings(lib):
     assert lib.env_mips_floats(2, 1) == 8
     for bad in ((512, 255), (500, 250), (256, 256), (0, 0), (2 * 16384, 16384)):
         assert lib.env_mips_floats(*bad) == 0
-    # min-max pyramid, levels 0..top with ceil halving, two floats per texel
+    # depth pyramid, levels 0..top with ceil halving, four floats per texel
+    # (own pair, parent's pair), at most 4 GiB
     def hiz(w, h):
         n = w * h
         while w > 1 or h > 1:
             w, h = (w + 1) // 2, (h + 1) // 2
             n += w * h
-        return 2 * n
-    for w, h in ((1920, 1080), (1, 1), (7, 3), (3840, 2160), (16384, 1)):
+        return 4 * n if 16 * n <= 2 ** 32 - 16 else 0
+    for w, h in ((1920, 1080), (1, 1), (7, 3), (3840, 2160), (16384, 1), (16384, 12000),
+                 (16384, 16384)):
         assert lib.hiz_floats(w, h) == hiz(w, h)
+    assert lib.hiz_floats(16384, 16384) == 0
     assert lib.hiz_floats(0, 5) == 0 and lib.hiz_floats(16385, 2) == 0
     for s in (0, -1, -2, -3, -4, -5):
         assert lib.status_string(s) and lib.status_string(s) != "unknown status"

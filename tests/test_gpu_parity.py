@@ -73,17 +73,26 @@ def test_hiz_pyramid_bit_exact(h, w, th):
     rng = np.random.default_rng(h * 7 + w)
     d = rng.uniform(0.5, 50, (h, w)).astype(np.float32)
     d[rng.uniform(size=(h, w)) < 0.1] = np.inf
-    got = ssr.hiz_build(torch.from_numpy(d).cuda(), th).cpu().numpy().reshape(-1, 2)
+    got = ssr.hiz_build(torch.from_numpy(d).cuda(), th).cpu().numpy().reshape(-1, 4)
     mins = oracle.march.hiz_pyramid(d)
     maxs = oracle.march.hiz_max_pyramid(d)
     one, t32 = np.float32(1.0), np.float32(th)
-    # stored as correctly rounded float32 quotients (1/min D, 1/(max D + th)),
-    # the sum rounded to float32 first
-    want = np.concatenate([np.stack([one / a.reshape(-1).astype(np.float32),
-                                     one / (b.reshape(-1).astype(np.float32) + t32)], 1)
-                           for a, b in zip(mins, maxs)])
+    # each texel: its own pair, correctly rounded float32 quotients
+    # (1/min D, 1/(max D + th)) with the sum rounded to float32 first, then
+    # the pair of its parent (x/2, y/2) one level up (the top texel: its own)
+    pairs = [np.stack([one / a.astype(np.float32), one / (b.astype(np.float32) + t32)], -1)
+             for a, b in zip(mins, maxs)]
+    want = []
+    for L, own in enumerate(pairs):
+        par = pairs[min(L + 1, len(pairs) - 1)]
+        hh, ww = own.shape[:2]
+        if L + 1 < len(pairs):
+            par = par[np.arange(hh)[:, None] // 2, np.arange(ww)[None, :] // 2]
+        want.append(np.concatenate([own, par], -1).reshape(-1, 4))
+    want = np.concatenate(want)
     assert got.shape == want.shape
-    assert np.array_equal(got, want)
+    assert np.array_equal(got[:, :2], want[:, :2]), "own pairs"
+    assert np.array_equal(got[:, 2:], want[:, 2:]), "parent pairs"
 
 
 def test_hiz_build_rejects_bad_thickness():
