@@ -31,8 +31,8 @@ HBM_PEAK_GBS = 8000.0
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--config", default="c2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true", help="FP32 only")
@@ -61,19 +61,23 @@ def upload(scene, dtype, dev):
 
 
 # Algorithmic work model of one frame (the method's own reads, writes and
-# arithmetic; not what the implementation happens to issue).
+# arithmetic; not what the implementation happens to issue), split between
+# the trace kernel (sampling and march) and the resolve kernel (shading).
 #
-# Bytes: every pixel's depth (4 B) and RGB output (12 B); a background pixel
-# one environment texel (12 B), any other pixel its two material records
-# (normal/roughness and albedo/metalness: 32 B FP32, 16 B FP16/BF16); per march
-# iteration the depth texels it reads (the hierarchical march reads the
-# (min, max) pair of a cell and of its parent: 16 B; the linear march one
-# depth: 4 B); per ray one radiance read (12 B FP32 or 6 B FP16 at a hit pixel,
-# 12 B of environment otherwise).  The pyramid build reads the depth once and
-# writes one pair per texel.
+# Bytes.  Trace: every pixel's depth (4 B); a non-background pixel its
+# normal/roughness record (16 B FP32, 8 B FP16/BF16); per march iteration the
+# pyramid texel it reads (hierarchical: the cell's pair and its parent's,
+# 16 B; linear: one depth, 4 B).  Resolve: every pixel's RGB output (12 B); a
+# background pixel one environment texel (12 B), any other pixel its two
+# material records (32 B FP32, 16 B FP16/BF16); per ray one radiance read
+# (12 B FP32 or 6 B FP16 at a hit pixel, 12 B of environment otherwise).  The
+# per-sample hit codes passed between the two are the split's own traffic
+# and not counted.  The pyramid build reads the depth once and writes one
+# 16 B texel per pyramid texel.
 #
 # Operations: 32-bit lane operations of the method's own formulation (an
-# FMA, a compare, a select, a transcendental instruction each count one):
+# FMA, a compare, a select, a transcendental instruction each count one).
+# Trace:
 OPS_PER_HIZ_ITER = 54     # two cells (the cell and its parent), each: cell index 2,
                           # exit parameter per axis 3 (x2), nearer exit 1, ray
                           # inverse depth at the exit 1, texel address 2, front
@@ -84,15 +88,16 @@ OPS_PER_SAMPLE = 156      # Philox4x32-10 98 and the two 24-bit uniforms 6; the
                           # visible-normal sample (stretch, normalise, cap point,
                           # sin/cos, un-stretch, normalise) 30; to world 9;
                           # reflection and the two cosines 13
-OPS_PER_RAY = 64          # ray segment (view direction 9, end point 8, projection
-                          # 10, screen deltas and inverse depths 8); Schlick
-                          # Fresnel 8, Smith G1 6, product 3; compensated sum 12
+OPS_PER_SEGMENT = 35      # view direction 9, end point 8, projection 10, screen
+                          # deltas and inverse depths 8
+OPS_PER_PIXEL_SETUP = 48  # un-projection 3, view vector 17, normal 7, clamps 2,
+                          # frame 10, local view vector 9
+# Resolve:
+OPS_PER_WEIGHT = 29       # Schlick Fresnel 8, Smith G1 6, product 3; compensated sum 12
 OPS_PER_HIT = 2           # radiance texel address
 OPS_PER_MISS = 47         # equirect angles 25, texel coordinates 6, weights 4, blend 12
-OPS_PER_PIXEL = 132       # un-projection 3, view vector 17, normal 7, clamps 2, F0 3,
-                          # frame 10, local view vector 9; direct diffuse: level 3,
-                          # angles 25, two bilinear lookups 44, blend 3, albedo 4;
-                          # output 3
+OPS_PER_PIXEL_SHADE = 85  # F0 3; direct diffuse: level 3, angles 25, two bilinear
+                          # lookups 44, blend 3, albedo 4; output 3
 # Peak: 157.3 TFLOP/s FP32 vector counts an FMA as two flops and a packed
 # instruction as two lanes; single 32-bit lane operations issue at
 # 256 CUs x 64 lanes x 2.4 GHz.
@@ -100,11 +105,11 @@ VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 
 
 def work_model(scene, hits, steps, dtype):
-    """Algorithmic bytes and operations of the shading kernel and bytes of the
-    pyramid build, from the kernel's own hit codes and iteration counts."""
+    """Algorithmic bytes and operations of the trace and resolve kernels and
+    bytes of the pyramid build, from the frame's hit codes and iteration
+    counts."""
     P = scene.width * scene.height
-    mat = 32 if dtype == "f32" else 16
-    br_hit = 12 if dtype == "f32" else 6
+    half = dtype != "f32"
     n_iter = int(steps.sum(dtype=np.int64))
     rays = (hits >= 0) | (hits == -1) | (hits == -4)  # samples that reach a radiance lookup
     n_hit = int((hits >= 0).sum())
@@ -112,12 +117,14 @@ def work_model(scene, hits, steps, dtype):
     n_env = n_rays - n_hit
     fg = int((hits[..., 0] != -3).sum())
     hiz = scene.params["march"] == 1
-    shade_bytes = (P * 16 + fg * mat + (P - fg) * 12 + (16 if hiz else 4) * n_iter
-                   + br_hit * n_hit + 12 * n_env)
     n_drawn = int((hits != -3).sum() - (hits == -5).sum())
-    shade_ops = ((OPS_PER_HIZ_ITER if hiz else OPS_PER_LINEAR_STEP) * n_iter
-                 + OPS_PER_SAMPLE * n_drawn + OPS_PER_RAY * n_rays + OPS_PER_HIT * n_hit
-                 + OPS_PER_MISS * n_env + OPS_PER_PIXEL * fg)
+    trace_bytes = P * 4 + fg * (8 if half else 16) + (16 if hiz else 4) * n_iter
+    trace_ops = ((OPS_PER_HIZ_ITER if hiz else OPS_PER_LINEAR_STEP) * n_iter
+                 + OPS_PER_SAMPLE * n_drawn + OPS_PER_SEGMENT * n_rays + OPS_PER_PIXEL_SETUP * fg)
+    resolve_bytes = (P * 12 + fg * (16 if half else 32) + (P - fg) * 12
+                     + (6 if half else 12) * n_hit + 12 * n_env)
+    resolve_ops = (OPS_PER_WEIGHT * n_rays + OPS_PER_HIT * n_hit + OPS_PER_MISS * n_env
+                   + (OPS_PER_PIXEL_SETUP + OPS_PER_PIXEL_SHADE) * fg)
     texels, w, h = 0, scene.width, scene.height
     while True:
         texels += w * h
@@ -125,12 +132,13 @@ def work_model(scene, hits, steps, dtype):
             break
         w, h = (w + 1) // 2, (h + 1) // 2
     hiz_bytes = P * 4 + 16 * int(texels)
-    return dict(bytes_shade=shade_bytes, ops_shade=shade_ops, bytes_hiz=hiz_bytes,
+    return dict(bytes_trace=trace_bytes, ops_trace=trace_ops, bytes_resolve=resolve_bytes,
+                ops_resolve=resolve_ops, bytes_hiz=hiz_bytes,
                 mean_iters=n_iter / max(1, n_rays), hit_frac=n_hit / max(1, n_rays),
                 iterations=n_iter, rays=n_rays)
 
 
-COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "shade_hiz_kernel_c2_1080p_16spp_counters.md")
+COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "trace_hiz_kernel_c2_1080p_16spp_counters.md")
 
 
 def kernel_sources_digest():
@@ -178,16 +186,22 @@ def time_gpu(ctx, scene, dtype, steps, warmup, dev, mips):
     cam = ssr.make_camera(scene.camera)
     prm = ssr.make_params(scene.params)
 
+    codes = torch.empty((H, W, S), dtype=torch.int32, device=dev)
+
     def step(ev=None):
         if ev is not None:
             ev[0].record(stream)
         ssr.hiz_build(t["depth"], scene.params["thickness"], out=hiz, stream=stream)
         if ev is not None:
             ev[1].record(stream)
-        ctx.shade(cam, t["depth"], t["normal_rough"], t["albedo_metal"], t["radiance"], t["env"],
-                  prm, env_mips=mips, hiz=hiz, out=out, stream=stream)
+        ctx.trace(cam, t["depth"], t["normal_rough"], t["albedo_metal"], t["radiance"], prm,
+                  hiz=hiz, hits=codes, stream=stream)
         if ev is not None:
             ev[2].record(stream)
+        ctx.resolve(cam, t["depth"], t["normal_rough"], t["albedo_metal"], t["radiance"], t["env"],
+                    prm, codes, env_mips=mips, out=out, stream=stream)
+        if ev is not None:
+            ev[3].record(stream)
 
     # untimed: the per-sample iteration counts and hit codes for the byte model
     hits = torch.empty((H, W, S), dtype=torch.int32, device=dev)
@@ -200,7 +214,7 @@ def time_gpu(ctx, scene, dtype, steps, warmup, dev, mips):
 
     for _ in range(warmup):
         step()
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
     start = torch.cuda.Event(enable_timing=True)
     end = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -213,12 +227,14 @@ def time_gpu(ctx, scene, dtype, steps, warmup, dev, mips):
     wall = time.perf_counter() - t0
     total_ms = start.elapsed_time(end)
     hiz_ms = [e[0].elapsed_time(e[1]) for e in evs]
-    shade_ms = [e[1].elapsed_time(e[2]) for e in evs]
+    trace_ms = [e[1].elapsed_time(e[2]) for e in evs]
+    resolve_ms = [e[2].elapsed_time(e[3]) for e in evs]
+    frame_ms = [e[0].elapsed_time(e[3]) for e in evs]
     work = work_model(scene, hits_np, steps_np, dtype)
     return dict(ms_per_step=total_ms / steps, wall_ms_per_step=1e3 * wall / steps,
-                shade_ms=float(np.mean(shade_ms)), shade_ms_p50=float(np.median(shade_ms)),
-                shade_ms_p99=float(np.quantile(shade_ms, 0.99)), hiz_ms=float(np.mean(hiz_ms)),
-                **work)
+                frame_ms_p50=float(np.median(frame_ms)), frame_ms_p99=float(np.quantile(frame_ms, 0.99)),
+                trace_ms=float(np.mean(trace_ms)), resolve_ms=float(np.mean(resolve_ms)),
+                hiz_ms=float(np.mean(hiz_ms)), **work)
 
 
 def _oracle_rows(args):
@@ -306,9 +322,8 @@ def main():
         del src, dst, flush
     rays = scene.width * scene.height * scene.params["spp"]
     r32 = res["f32"]
-    kernel_s = r32["shade_ms"] * 1e-3
-    ops_rate = r32["ops_shade"] / kernel_s / 1e12
-    gbs = r32["bytes_shade"] / kernel_s / 1e9
+    trace_s, resolve_s = r32["trace_ms"] * 1e-3, r32["resolve_ms"] * 1e-3
+    ops_rate = r32["ops_trace"] / trace_s / 1e12
     line = {
         "metric": "Mrays/s + ms/frame at 1080p 16spp (FP32 vs FP16 G-buf); p50/p99 serve latency",
         "value": rays / (r32["ms_per_step"] * 1e-3) / 1e6,
@@ -331,19 +346,26 @@ def main():
         "roofline": {"bound": "alu", "achieved": ops_rate, "peak": VALU_PEAK_TOPS,
                      "unit": "Tops/s", "frac": ops_rate / VALU_PEAK_TOPS,
                      "traffic": measured_traffic() if args.config == "c2" else None,
-                     "kernel": "shade_hiz_kernel<f32>", "kernel_ms": r32["shade_ms"],
-                     "algorithmic_ops": r32["ops_shade"],
+                     "kernel": "trace_hiz_kernel<f32>", "kernel_ms": r32["trace_ms"],
+                     "algorithmic_ops": r32["ops_trace"],
                      "march_iterations": r32["iterations"], "rays": r32["rays"],
-                     "mean_iterations_per_ray": r32["mean_iters"]},
-        "hbm": {"achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
-                "algorithmic_bytes": r32["bytes_shade"]},
-        "shade_ms_p50": r32["shade_ms_p50"], "shade_ms_p99": r32["shade_ms_p99"],
+                     "mean_iterations_per_ray": r32["mean_iters"],
+                     "hbm_algorithmic_bytes": r32["bytes_trace"],
+                     "hbm_gbs": r32["bytes_trace"] / trace_s / 1e9},
+        "resolve": {"kernel": "resolve_kernel<f32>", "kernel_ms": r32["resolve_ms"],
+                    "alu_tops": r32["ops_resolve"] / resolve_s / 1e12,
+                    "alu_frac": r32["ops_resolve"] / resolve_s / 1e12 / VALU_PEAK_TOPS,
+                    "hbm_gbs": r32["bytes_resolve"] / resolve_s / 1e9,
+                    "hbm_frac": r32["bytes_resolve"] / resolve_s / 1e9 / HBM_PEAK_GBS},
+        "frame_ms_p50": r32["frame_ms_p50"], "frame_ms_p99": r32["frame_ms_p99"],
         "hiz_build_ms": r32["hiz_ms"],
+        "hiz_build_gbs": r32["bytes_hiz"] / (r32["hiz_ms"] * 1e-3) / 1e9,
     }
     for dt in ("f16", "bf16"):
         if dt in res:
             line[dt] = {"value": rays / (res[dt]["ms_per_step"] * 1e-3) / 1e6,
-                        "ms_per_step": res[dt]["ms_per_step"], "shade_ms": res[dt]["shade_ms"]}
+                        "ms_per_step": res[dt]["ms_per_step"], "trace_ms": res[dt]["trace_ms"],
+                        "resolve_ms": res[dt]["resolve_ms"]}
     if cpu is not None:
         line["cpu_baseline"] = cpu
     ctx.close()

@@ -135,19 +135,40 @@ int ssr_ctx_create(int device, ssr_ctx** out);
  * accepted. */
 void ssr_ctx_destroy(ssr_ctx* ctx);
 
-/* Shade one frame (Sec. 3.2 diffuse + Sec. 3.3 Monte-Carlo specular).
+/* Shade one frame (Sec. 3.2 diffuse + Sec. 3.3 Monte-Carlo specular):
+ * ssr_trace followed by ssr_resolve on `stream`.
  *   out_rgb   [H][W][3] float32, written: linear HDR c_d + c_s' (no tone map).
- *   out_hits  NULL or [H][W][spp] int32: per-sample hit pixel or SSR_HIT_* code.
+ *   out_hits  NULL or [H][W][spp] int32: per-sample hit pixel or SSR_HIT_* code
+ *             (NULL: the codes go to the context's workspace).
  *   out_steps NULL or [H][W][spp] int32: march iterations each sample used.
  * Sample s of pixel q = j*W + i draws Philox4x32-10 with counter
  * (q, s, frame, 0): u1 = (x0 >> 8) 2^-24 picks the azimuth, u2 = (x1 >> 8) 2^-24
- * the cap height of the visible-normal sample.  width or height 0 is a no-op.
- * In hiz mode the depth pyramid is built in the context's workspace unless
- * gbuf->hiz supplies it; the env mip chain likewise unless env->mips does.
- * Both builds run on `stream` before the shading kernel. */
+ * the cap height of the visible-normal sample.  width or height 0 is a no-op;
+ * W H must leave the depth pyramid below 4 GiB (about 200 Mpixels), else
+ * SSR_E_ARG.  In hiz mode the depth pyramid is built in the context's
+ * workspace unless gbuf->hiz supplies it; the env mip chain likewise unless
+ * env->mips does.  Both builds run on `stream` before the kernels. */
 int ssr_shade(ssr_ctx* ctx, const ssr_camera* cam, const ssr_gbuffer* gbuf,
               const ssr_env* env, const ssr_params* params, float* out_rgb,
               int32_t* out_hits, int32_t* out_steps, void* stream);
+
+/* The march half of ssr_shade (Sec. 3.3 sampling, Appendix D march): write
+ * every sample's hit code to out_hits ([H][W][spp] int32, required) and,
+ * unless NULL, its iteration count to out_steps.  Reads depth and the
+ * normal/roughness buffer (and gbuf->hiz); the other buffers and the
+ * environment are not used.  Same validation as ssr_shade. */
+int ssr_trace(ssr_ctx* ctx, const ssr_camera* cam, const ssr_gbuffer* gbuf,
+              const ssr_params* params, int32_t* out_hits, int32_t* out_steps, void* stream);
+
+/* The shading half of ssr_shade (Sec. 3.2, Sec. 3.3 estimator): out_rgb from
+ * per-sample hit codes `hits` [H][W][spp] int32 (as ssr_trace writes them, or
+ * any codes to replay).  The sample directions are drawn again from the same
+ * Philox counters; a code >= 0 reads the first-pass radiance of that pixel,
+ * SSR_HIT_OFFSCREEN and SSR_HIT_CAP the environment along the sample; a code
+ * outside [SSR_HIT_SKIPPED, W H) counts as SSR_HIT_INVALID (weight 0). */
+int ssr_resolve(ssr_ctx* ctx, const ssr_camera* cam, const ssr_gbuffer* gbuf,
+                const ssr_env* env, const ssr_params* params, const int32_t* hits,
+                float* out_rgb, void* stream);
 
 /* Number of floats of the env mip-chain buffer for a We x He map (0 if the
  * dimensions are invalid). */

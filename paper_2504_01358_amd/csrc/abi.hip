@@ -173,94 +173,153 @@ int ssr_philox4x32_10(const uint32_t* ctr, const uint32_t* key, int64_t n, uint3
     return hip_status(ssr::launch_philox(ctr, key, n, out, static_cast<hipStream_t>(stream)));
 }
 
-int ssr_shade(ssr_ctx* ctx, const ssr_camera* cam, const ssr_gbuffer* g, const ssr_env* env,
-              const ssr_params* p, float* out_rgb, int32_t* out_hits, int32_t* out_steps,
-              void* stream) {
-    if (!ctx || !g || !env) return SSR_E_ARG;
+}  // extern "C"
+
+namespace {
+
+// Validate the arguments common to the shading calls and fill `a` with
+// everything but the output pointers.  Returns SSR_OK, or 1 for an empty
+// image (nothing to do), or an error.
+int prepare(ssr_ctx* ctx, const ssr_camera* cam, const ssr_gbuffer* g, const ssr_env* env,
+            const ssr_params* p, bool need_env, ssr::ShadeArgs* a, ssr::EnvLayout* env_lay,
+            ssr::HizLayout* hiz_lay) {
+    if (!ctx || !g || (need_env && !env)) return SSR_E_ARG;
     int st = check_camera(cam);
     if (st != SSR_OK) return st;
     st = check_params(p);
     if (st != SSR_OK) return st;
     if (g->dtype != SSR_F32 && g->dtype != SSR_F16 && g->dtype != SSR_BF16) return SSR_E_DTYPE;
-    ssr::EnvLayout env_lay;
-    if (!env->rgb || !ssr::make_env_layout(env->width, env->height, &env_lay)) return SSR_E_ARG;
-    if (cam->width == 0 || cam->height == 0) return SSR_OK;
-    if (!g->depth || !g->normal_rough || !g->albedo_metal || !g->radiance || !out_rgb)
+    if (need_env && (!env->rgb || !ssr::make_env_layout(env->width, env->height, env_lay)))
         return SSR_E_ARG;
-    ssr::HizLayout hiz_lay;
-    if (!ssr::make_hiz_layout(cam->width, cam->height, &hiz_lay)) return SSR_E_ARG;
-
+    if (cam->width == 0 || cam->height == 0) return 1;
+    if (!g->depth || !g->normal_rough || !g->albedo_metal || !g->radiance) return SSR_E_ARG;
+    // (the hierarchical march needs the pyramid; the layout also bounds W H)
+    if (!ssr::make_hiz_layout(cam->width, cam->height, hiz_lay)) return SSR_E_ARG;
     if (hipSetDevice(ctx->device) != hipSuccess) return SSR_E_HIP;
-    hipStream_t s = static_cast<hipStream_t>(stream);
 
-    const float4* mips = reinterpret_cast<const float4*>(env->mips);
-    if (!mips) {
-        st = ensure(&ctx->mips, &ctx->mips_cap, env_lay.total);
-        if (st != SSR_OK) return st;
-        st = hip_status(ssr::launch_env_mips(env->rgb, env_lay, ctx->mips, s));
-        if (st != SSR_OK) return st;
-        mips = ctx->mips;
+    memset(a, 0, sizeof(*a));
+    a->W = cam->width;
+    a->H = cam->height;
+    for (int k = 0; k < 3; ++k) {
+        a->pos[k] = cam->pos[k];
+        a->right[k] = cam->rot[k];
+        a->up[k] = cam->rot[3 + k];
+        a->fwd[k] = cam->rot[6 + k];
     }
+    a->fx = cam->fx;
+    a->fy = cam->fy;
+    a->cx = cam->cx;
+    a->cy = cam->cy;
+    a->z_near = cam->z_near;
+    a->depth = g->depth;
+    a->normal_rough = g->normal_rough;
+    a->albedo_metal = g->albedo_metal;
+    a->radiance = g->radiance;
+    a->hiz_lay = *hiz_lay;
+    if (need_env) a->env_lay = *env_lay;
+    a->spp = p->spp;
+    a->max_steps = p->max_steps;
+    // linear march: samples t_k = k * step_len for k = 1..K, K = min(max_steps,
+    // floor(max_dist / step_len)), evaluated in double as the specification states
+    if (p->march == SSR_MARCH_LINEAR) {
+        const double k = floor(static_cast<double>(p->max_dist) / static_cast<double>(p->step_len));
+        a->linear_samples = k < static_cast<double>(p->max_steps) ? static_cast<int>(k) : p->max_steps;
+    }
+    a->step_len = p->step_len;
+    a->max_dist = p->max_dist;
+    a->thickness = p->thickness;
+    a->key0 = static_cast<uint32_t>(p->seed & 0xFFFFFFFFu);
+    a->key1 = static_cast<uint32_t>(p->seed >> 32);
+    a->frame = p->frame;
+    a->flags = p->flags;
+    a->tile_counter = ctx->counter;
+    return SSR_OK;
+}
+
+// The env mip chain: the caller's, or built in the workspace.
+int env_mips(ssr_ctx* ctx, const ssr_env* env, const ssr::EnvLayout& lay, hipStream_t s,
+             const float4** out) {
+    *out = reinterpret_cast<const float4*>(env->mips);
+    if (*out) return SSR_OK;
+    int st = ensure(&ctx->mips, &ctx->mips_cap, lay.total);
+    if (st != SSR_OK) return st;
+    st = hip_status(ssr::launch_env_mips(env->rgb, lay, ctx->mips, s));
+    *out = ctx->mips;
+    return st;
+}
+
+// Trace into `codes`: the hierarchical march builds the pyramid first unless
+// the caller supplies it.
+int trace(ssr_ctx* ctx, const ssr_gbuffer* g, const ssr_params* p, ssr::ShadeArgs* a,
+          const ssr::HizLayout& hiz_lay, int32_t* codes, int32_t* steps, hipStream_t s) {
     const float4* hiz = reinterpret_cast<const float4*>(g->hiz);
     if (p->march == SSR_MARCH_HIZ && !hiz) {
-        st = ensure(&ctx->hiz, &ctx->hiz_cap, hiz_lay.total);
+        int st = ensure(&ctx->hiz, &ctx->hiz_cap, hiz_lay.total);
         if (st != SSR_OK) return st;
         st = hip_status(ssr::launch_hiz(g->depth, hiz_lay, p->thickness, ctx->hiz, s));
         if (st != SSR_OK) return st;
         hiz = ctx->hiz;
     }
+    a->hiz = hiz;
+    a->codes = codes;
+    a->steps = steps;
+    return hip_status(ssr::launch_trace(*a, g->dtype, p->march, ctx->cu_count, s));
+}
+
+}  // namespace
+
+extern "C" {
+
+int ssr_trace(ssr_ctx* ctx, const ssr_camera* cam, const ssr_gbuffer* g, const ssr_params* p,
+              int32_t* out_hits, int32_t* out_steps, void* stream) {
+    ssr::ShadeArgs a;
+    ssr::EnvLayout env_lay;
+    ssr::HizLayout hiz_lay;
+    int st = prepare(ctx, cam, g, nullptr, p, false, &a, &env_lay, &hiz_lay);
+    if (st != SSR_OK) return st == 1 ? SSR_OK : st;
+    if (!out_hits) return SSR_E_ARG;
+    return trace(ctx, g, p, &a, hiz_lay, out_hits, out_steps, static_cast<hipStream_t>(stream));
+}
+
+int ssr_resolve(ssr_ctx* ctx, const ssr_camera* cam, const ssr_gbuffer* g, const ssr_env* env,
+                const ssr_params* p, const int32_t* hits, float* out_rgb, void* stream) {
+    ssr::ShadeArgs a;
+    ssr::EnvLayout env_lay;
+    ssr::HizLayout hiz_lay;
+    int st = prepare(ctx, cam, g, env, p, true, &a, &env_lay, &hiz_lay);
+    if (st != SSR_OK) return st == 1 ? SSR_OK : st;
+    if (!hits || !out_rgb) return SSR_E_ARG;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    st = env_mips(ctx, env, env_lay, s, &a.env);
+    if (st != SSR_OK) return st;
+    a.codes = const_cast<int32_t*>(hits);  // read only by the resolve kernel
+    a.out = out_rgb;
+    return hip_status(ssr::launch_resolve(a, g->dtype, s));
+}
+
+int ssr_shade(ssr_ctx* ctx, const ssr_camera* cam, const ssr_gbuffer* g, const ssr_env* env,
+              const ssr_params* p, float* out_rgb, int32_t* out_hits, int32_t* out_steps,
+              void* stream) {
+    ssr::ShadeArgs a;
+    ssr::EnvLayout env_lay;
+    ssr::HizLayout hiz_lay;
+    int st = prepare(ctx, cam, g, env, p, true, &a, &env_lay, &hiz_lay);
+    if (st != SSR_OK) return st == 1 ? SSR_OK : st;
+    if (!out_rgb) return SSR_E_ARG;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    st = env_mips(ctx, env, env_lay, s, &a.env);
+    if (st != SSR_OK) return st;
     int32_t* codes = out_hits;
-    if (p->march == SSR_MARCH_HIZ && !codes) {
+    if (!codes) {
         const int64_t n = static_cast<int64_t>(cam->width) * cam->height * p->spp;
         st = ensure(&ctx->codes, &ctx->codes_cap, n);
         if (st != SSR_OK) return st;
         codes = ctx->codes;
     }
-
-    ssr::ShadeArgs a;
-    memset(&a, 0, sizeof(a));
-    a.W = cam->width;
-    a.H = cam->height;
-    for (int k = 0; k < 3; ++k) {
-        a.pos[k] = cam->pos[k];
-        a.right[k] = cam->rot[k];
-        a.up[k] = cam->rot[3 + k];
-        a.fwd[k] = cam->rot[6 + k];
-    }
-    a.fx = cam->fx;
-    a.fy = cam->fy;
-    a.cx = cam->cx;
-    a.cy = cam->cy;
-    a.z_near = cam->z_near;
-    a.depth = g->depth;
-    a.normal_rough = g->normal_rough;
-    a.albedo_metal = g->albedo_metal;
-    a.radiance = g->radiance;
-    a.env = mips;
-    a.env_lay = env_lay;
-    a.hiz = hiz;
-    a.hiz_lay = hiz_lay;
-    a.spp = p->spp;
-    a.max_steps = p->max_steps;
-    // linear march: samples t_k = k * step_len for k = 1..K, K = min(max_steps,
-    // floor(max_dist / step_len)), evaluated in double as the specification states
-    {
-        const double k = floor(static_cast<double>(p->max_dist) / static_cast<double>(p->step_len));
-        a.linear_samples = k < static_cast<double>(p->max_steps) ? static_cast<int>(k) : p->max_steps;
-    }
-    a.step_len = p->step_len;
-    a.max_dist = p->max_dist;
-    a.thickness = p->thickness;
-    a.key0 = static_cast<uint32_t>(p->seed & 0xFFFFFFFFu);
-    a.key1 = static_cast<uint32_t>(p->seed >> 32);
-    a.frame = p->frame;
-    a.flags = p->flags;
+    st = trace(ctx, g, p, &a, hiz_lay, codes, out_steps, s);
+    if (st != SSR_OK) return st;
     a.out = out_rgb;
-    a.hits = out_hits;
-    a.steps = out_steps;
-    a.codes = codes;
-    a.tile_counter = ctx->counter;
-    return hip_status(ssr::launch_shade(a, g->dtype, p->march, ctx->cu_count, s));
+    return hip_status(ssr::launch_resolve(a, g->dtype, s));
 }
 
 }  // extern "C"

@@ -52,18 +52,20 @@ struct ShadeArgs {
     float step_len, max_dist, thickness;
     uint32_t key0, key1, frame, flags;
     float* out;
-    int32_t* hits;
     int32_t* steps;
-    int32_t* codes;           // hierarchical path: per-sample hit codes [H][W][spp]
-    int* tile_counter;        // hierarchical path: next tile of the trace kernel
+    int32_t* codes;           // per-sample hit codes [H][W][spp]
+    int* tile_counter;        // hierarchical trace: next tile
 };
 
 hipError_t launch_env_mips(const float* rgb, const EnvLayout& lay, float4* mips,
                            hipStream_t stream);
 hipError_t launch_hiz(const float* depth, const HizLayout& lay, float thickness, float4* pyramid,
                       hipStream_t stream);
-hipError_t launch_shade(const ShadeArgs& args, int dtype, int march, int cu_count,
+// Per-sample hit codes into args.codes (and iteration counts into args.steps).
+hipError_t launch_trace(const ShadeArgs& args, int dtype, int march, int cu_count,
                         hipStream_t stream);
+// The image from the hit codes in args.codes.
+hipError_t launch_resolve(const ShadeArgs& args, int dtype, hipStream_t stream);
 hipError_t launch_philox(const uint32_t* ctr, const uint32_t* key, int64_t n, uint32_t* out,
                          hipStream_t stream);
 

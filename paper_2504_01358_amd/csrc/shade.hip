@@ -385,12 +385,13 @@ __device__ __forceinline__ void write_out(const ShadeArgs& a, int64_t q, float3 
         make_float3(cd.x + sum[0] * invS, cd.y + sum[1] * invS, cd.z + sum[2] * invS);
 }
 
-// -------------------------------------------------- linear-march kernel --
+// ------------------------------------------------------ linear-march trace --
 //
-// Workgroups of 256 threads shade 16 x 16 pixel tiles; each wave64 takes an
-// 8 x 8 quadrant; each thread shades one pixel, its samples in order.
+// Workgroups of 256 threads take 16 x 16 pixel tiles; each wave64 an 8 x 8
+// quadrant; each thread marches its pixel's samples in order, in lockstep
+// with the wave, and writes their hit codes.
 template <int DT>
-__global__ __launch_bounds__(256) void shade_linear_kernel(const ShadeArgs a) {
+__global__ __launch_bounds__(256) void trace_linear_kernel(const ShadeArgs a) {
     const int tiles_x = (a.W + 15) / 16;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int i = (blockIdx.x % tiles_x) * 16 + (wave & 1) * 8 + (lane & 7);
@@ -400,7 +401,6 @@ __global__ __launch_bounds__(256) void shade_linear_kernel(const ShadeArgs a) {
     const int S = a.spp;
     const Pixel P = setup_pixel<DT>(a, i, j, q);
     const int fill = fill_code(a, P);
-    float sum[3] = {0.0f, 0.0f, 0.0f}, cmp[3] = {0.0f, 0.0f, 0.0f};
     for (int s = 0; s < S; ++s) {
         int code = fill, iters = 0;
         if (P.trace) {
@@ -409,13 +409,11 @@ __global__ __launch_bounds__(256) void shade_linear_kernel(const ShadeArgs a) {
                 const MarchResult r = march_linear(a, i, j, v3(P.X0, P.Y0, P.D), world_to_view(a, d.l));
                 code = r.code;
                 iters = r.iters;
-                accumulate<DT>(a, P, d, code, sum, cmp);
             }
         }
-        if (a.hits) a.hits[q * S + s] = code;
+        a.codes[q * S + s] = code;
         if (a.steps) a.steps[q * S + s] = iters;
     }
-    write_out(a, q, direct_term(a, P, i, j), sum);
 }
 
 // ---------------------------------------------------- hierarchical path --
@@ -587,7 +585,9 @@ __global__ __launch_bounds__(256) void resolve_kernel(const ShadeArgs a) {
         const int32_t* codes = a.codes + q * S;
 #pragma unroll 1
         for (int s = 0; s < S; ++s) {
-            const int code = codes[s];
+            int code = codes[s];
+            // (a code naming no pixel of this frame contributes nothing)
+            if (code >= a.W * a.H || code < SSR_HIT_SKIPPED) code = SSR_HIT_INVALID;
             if (code >= 0 || code == SSR_HIT_OFFSCREEN || code == SSR_HIT_CAP) {
                 const SampleDir d = sample_dir(a, P, q, s);
                 accumulate<DT>(a, P, d, code, sum, cmp);
@@ -603,28 +603,33 @@ int trace_grid(int cu_count, int W, int H) {
     return n_tiles < resident ? n_tiles : resident;
 }
 
-hipError_t launch_shade(const ShadeArgs& args, int dtype, int march, int cu_count,
+hipError_t launch_trace(const ShadeArgs& args, int dtype, int march, int cu_count,
                         hipStream_t stream) {
-    if (march == 0) {
+    if (march == SSR_MARCH_LINEAR) {
         const dim3 grid(((args.W + 15) / 16) * ((args.H + 15) / 16));
 #define SSR_LAUNCH(DT) \
-    hipLaunchKernelGGL((shade_linear_kernel<DT>), grid, dim3(256), 0, stream, args)
-        if (dtype == 0) SSR_LAUNCH(0);
-        else if (dtype == 1) SSR_LAUNCH(1);
+    hipLaunchKernelGGL((trace_linear_kernel<DT>), grid, dim3(256), 0, stream, args)
+        if (dtype == SSR_F32) SSR_LAUNCH(0);
+        else if (dtype == SSR_F16) SSR_LAUNCH(1);
         else SSR_LAUNCH(2);
 #undef SSR_LAUNCH
         return hipGetLastError();
     }
     hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, stream, args.tile_counter);
-    const dim3 tgrid(trace_grid(cu_count, args.W, args.H));
-    const dim3 rgrid(((args.W + 15) / 16) * ((args.H + 15) / 16));
-#define SSR_LAUNCH(DT)                                                                          \
-    do {                                                                                        \
-        hipLaunchKernelGGL((trace_hiz_kernel<DT>), tgrid, dim3(64), 0, stream, args);           \
-        hipLaunchKernelGGL((resolve_kernel<DT>), rgrid, dim3(256), 0, stream, args);            \
-    } while (0)
-    if (dtype == 0) SSR_LAUNCH(0);
-    else if (dtype == 1) SSR_LAUNCH(1);
+    const dim3 grid(trace_grid(cu_count, args.W, args.H));
+#define SSR_LAUNCH(DT) hipLaunchKernelGGL((trace_hiz_kernel<DT>), grid, dim3(64), 0, stream, args)
+    if (dtype == SSR_F32) SSR_LAUNCH(0);
+    else if (dtype == SSR_F16) SSR_LAUNCH(1);
+    else SSR_LAUNCH(2);
+#undef SSR_LAUNCH
+    return hipGetLastError();
+}
+
+hipError_t launch_resolve(const ShadeArgs& args, int dtype, hipStream_t stream) {
+    const dim3 grid(((args.W + 15) / 16) * ((args.H + 15) / 16));
+#define SSR_LAUNCH(DT) hipLaunchKernelGGL((resolve_kernel<DT>), grid, dim3(256), 0, stream, args)
+    if (dtype == SSR_F32) SSR_LAUNCH(0);
+    else if (dtype == SSR_F16) SSR_LAUNCH(1);
     else SSR_LAUNCH(2);
 #undef SSR_LAUNCH
     return hipGetLastError();

@@ -20,9 +20,9 @@ MARCH_LINEAR, MARCH_HIZ = 0, 1
 NO_DIRECT, NO_SPECULAR = 1, 2
 HIT_OFFSCREEN, HIT_INVALID, HIT_BACKGROUND, HIT_CAP, HIT_SKIPPED = -1, -2, -3, -4, -5
 
-SYMBOLS = ("ssr_ctx_create", "ssr_ctx_destroy", "ssr_shade", "ssr_env_mips_floats",
-           "ssr_env_build_mips", "ssr_hiz_floats", "ssr_hiz_build", "ssr_philox4x32_10",
-           "ssr_status_string")
+SYMBOLS = ("ssr_ctx_create", "ssr_ctx_destroy", "ssr_shade", "ssr_trace", "ssr_resolve",
+           "ssr_env_mips_floats", "ssr_env_build_mips", "ssr_hiz_floats", "ssr_hiz_build",
+           "ssr_philox4x32_10", "ssr_status_string")
 
 
 class SSRError(RuntimeError):
@@ -68,6 +68,10 @@ def _load():
     lib.ssr_ctx_destroy.restype = None
     lib.ssr_shade.argtypes = [vp, P(Camera), P(GBuffer), P(Env), P(Params), vp, vp, vp, vp]
     lib.ssr_shade.restype = ctypes.c_int
+    lib.ssr_trace.argtypes = [vp, P(Camera), P(GBuffer), P(Params), vp, vp, vp]
+    lib.ssr_trace.restype = ctypes.c_int
+    lib.ssr_resolve.argtypes = [vp, P(Camera), P(GBuffer), P(Env), P(Params), vp, vp, vp]
+    lib.ssr_resolve.restype = ctypes.c_int
     lib.ssr_env_mips_floats.argtypes = [ctypes.c_int32, ctypes.c_int32]
     lib.ssr_env_mips_floats.restype = ctypes.c_int64
     lib.ssr_env_build_mips.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, vp, vp]
@@ -163,13 +167,8 @@ class Context:
         except Exception:
             pass
 
-    def shade(self, camera, depth, normal_rough, albedo_metal, radiance, env, params,
-              env_mips=None, hiz=None, out=None, hits=None, steps=None, stream=None):
-        """Shade one frame; returns ``out`` [H][W][3] float32 (and fills the
-        optional int32 ``hits`` / ``steps`` [H][W][spp] tensors).  ``env_mips``
-        and ``hiz`` optionally supply prebuilt pyramids for these inputs."""
-        cam = camera if isinstance(camera, Camera) else make_camera(camera)
-        prm = params if isinstance(params, Params) else make_params(params)
+    @staticmethod
+    def _gbuf(cam, depth, normal_rough, albedo_metal, radiance, hiz):
         H, W = cam.height, cam.width
         _dev_tensor(depth, "depth", torch.float32, (H, W))
         dt = normal_rough.dtype
@@ -178,6 +177,15 @@ class Context:
         for name, t in (("normal_rough", normal_rough), ("albedo_metal", albedo_metal),
                         ("radiance", radiance)):
             _dev_tensor(t, name, dt, (H, W, 4))
+        if hiz is not None:
+            _dev_tensor(hiz, "hiz", torch.float32)
+            if hiz.numel() != hiz_floats(W, H):
+                raise ValueError("hiz has the wrong size for this depth buffer")
+        return GBuffer(depth.data_ptr(), normal_rough.data_ptr(), albedo_metal.data_ptr(),
+                       radiance.data_ptr(), _GBUF_DTYPES[dt], None if hiz is None else hiz.data_ptr())
+
+    @staticmethod
+    def _env(env, env_mips):
         _dev_tensor(env, "env", torch.float32)
         if env.dim() != 3 or env.shape[2] != 3:
             raise ValueError("env must be [He][We][3]")
@@ -185,24 +193,66 @@ class Context:
             _dev_tensor(env_mips, "env_mips", torch.float32)
             if env_mips.numel() != env_mips_floats(env.shape[1], env.shape[0]):
                 raise ValueError("env_mips has the wrong size for this env")
+        return Env(env.data_ptr(), int(env.shape[1]), int(env.shape[0]),
+                   None if env_mips is None else env_mips.data_ptr())
+
+    @staticmethod
+    def _out(out, cam, device):
         if out is None:
-            out = torch.empty((H, W, 3), dtype=torch.float32, device=depth.device)
-        _dev_tensor(out, "out", torch.float32, (H, W, 3))
+            out = torch.empty((cam.height, cam.width, 3), dtype=torch.float32, device=device)
+        _dev_tensor(out, "out", torch.float32, (cam.height, cam.width, 3))
+        return out
+
+    def shade(self, camera, depth, normal_rough, albedo_metal, radiance, env, params,
+              env_mips=None, hiz=None, out=None, hits=None, steps=None, stream=None):
+        """Shade one frame; returns ``out`` [H][W][3] float32 (and fills the
+        optional int32 ``hits`` / ``steps`` [H][W][spp] tensors).  ``env_mips``
+        and ``hiz`` optionally supply prebuilt pyramids for these inputs."""
+        cam = camera if isinstance(camera, Camera) else make_camera(camera)
+        prm = params if isinstance(params, Params) else make_params(params)
+        g = self._gbuf(cam, depth, normal_rough, albedo_metal, radiance, hiz)
+        e = self._env(env, env_mips)
+        out = self._out(out, cam, depth.device)
         for name, t in (("hits", hits), ("steps", steps)):
             if t is not None:
-                _dev_tensor(t, name, torch.int32, (H, W, prm.spp))
-        if hiz is not None:
-            _dev_tensor(hiz, "hiz", torch.float32)
-            if hiz.numel() != hiz_floats(W, H):
-                raise ValueError("hiz has the wrong size for this depth buffer")
-        g = GBuffer(depth.data_ptr(), normal_rough.data_ptr(), albedo_metal.data_ptr(),
-                    radiance.data_ptr(), _GBUF_DTYPES[dt], None if hiz is None else hiz.data_ptr())
-        e = Env(env.data_ptr(), int(env.shape[1]), int(env.shape[0]),
-                None if env_mips is None else env_mips.data_ptr())
+                _dev_tensor(t, name, torch.int32, (cam.height, cam.width, prm.spp))
         st = lib.ssr_shade(self._h, ctypes.byref(cam), ctypes.byref(g), ctypes.byref(e),
                            ctypes.byref(prm), _ptr(out), _ptr(hits), _ptr(steps),
                            _stream(stream, depth.device))
         _check(st, "ssr_shade")
+        return out
+
+    def trace(self, camera, depth, normal_rough, albedo_metal, radiance, params, hiz=None,
+              hits=None, steps=None, stream=None):
+        """Per-sample hit codes of a frame; returns ``hits`` [H][W][spp] int32
+        (and fills the optional ``steps``)."""
+        cam = camera if isinstance(camera, Camera) else make_camera(camera)
+        prm = params if isinstance(params, Params) else make_params(params)
+        g = self._gbuf(cam, depth, normal_rough, albedo_metal, radiance, hiz)
+        if hits is None:
+            hits = torch.empty((cam.height, cam.width, prm.spp), dtype=torch.int32,
+                               device=depth.device)
+        for name, t in (("hits", hits), ("steps", steps)):
+            if t is not None:
+                _dev_tensor(t, name, torch.int32, (cam.height, cam.width, prm.spp))
+        st = lib.ssr_trace(self._h, ctypes.byref(cam), ctypes.byref(g), ctypes.byref(prm),
+                           _ptr(hits), _ptr(steps), _stream(stream, depth.device))
+        _check(st, "ssr_trace")
+        return hits
+
+    def resolve(self, camera, depth, normal_rough, albedo_metal, radiance, env, params, hits,
+                env_mips=None, out=None, stream=None):
+        """The image from per-sample hit codes ``hits`` [H][W][spp] int32."""
+        cam = camera if isinstance(camera, Camera) else make_camera(camera)
+        prm = params if isinstance(params, Params) else make_params(params)
+        g = self._gbuf(cam, depth, normal_rough, albedo_metal, radiance, None)
+        e = self._env(env, env_mips)
+        out = self._out(out, cam, depth.device)
+        _dev_tensor(hits, "hits", torch.int32, (cam.height, cam.width, prm.spp))
+        st = lib.ssr_resolve(self._h, ctypes.byref(cam), ctypes.byref(g), ctypes.byref(e),
+                             ctypes.byref(prm), _ptr(hits), _ptr(out),
+                             _stream(stream, depth.device))
+        _check(st, "ssr_resolve")
         return out
 
 

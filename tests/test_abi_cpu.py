@@ -36,7 +36,7 @@ def declared_functions():
 
 def test_every_declared_symbol_is_exported(lib):
     names = declared_functions()
-    assert len(names) == 9, names
+    assert len(names) == 11, names
     raw = ctypes.CDLL(LIB)
     for n in names:
         assert hasattr(raw, n), n
@@ -107,6 +107,8 @@ def test_host_side_argument_checks(lib):
     byref = ctypes.byref
     # null context / structures: rejected before any device work
     assert raw.ssr_shade(None, byref(cam), byref(g), byref(e), byref(p), None, None, None, None) == -1
+    assert raw.ssr_trace(None, byref(cam), byref(g), byref(p), None, None, None) == -1
+    assert raw.ssr_resolve(None, byref(cam), byref(g), byref(e), byref(p), None, None, None) == -1
     assert raw.ssr_env_build_mips(None, 512, 256, None, None) == -1
     assert raw.ssr_hiz_build(None, 16, 16, 0.0, None, None) == -1
     assert raw.ssr_philox4x32_10(None, None, 0, None, None) == 0
