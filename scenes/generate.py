@@ -234,15 +234,15 @@ def rasterize(camera, objs, env):
     hit = best_id >= 0
     depth = np.full(dirs.shape[0], np.inf)
     depth[hit] = ((best_t[hit, None] * dirs[hit]) @ rot[2])
-    albedo = np.zeros((dirs.shape[0], 3))
-    rough = np.zeros(dirs.shape[0])
-    metal = np.zeros(dirs.shape[0])
+    # material of each pixel's object (row 0 of the tables: background, zeros)
+    mat_a = np.zeros((len(objs) + 1, 3))
+    mat_r = np.zeros(len(objs) + 1)
+    mat_m = np.zeros(len(objs) + 1)
     for k, obj in enumerate(objs):
-        sel = best_id == k
-        a, r, m = obj["mat"]
-        albedo[sel] = a
-        rough[sel] = r
-        metal[sel] = m
+        mat_a[k + 1], mat_r[k + 1], mat_m[k + 1] = obj["mat"]
+    albedo = mat_a[best_id + 1]
+    rough = mat_r[best_id + 1]
+    metal = mat_m[best_id + 1]
     nrm = np.zeros_like(best_n)
     nrm[hit] = _normalize(best_n[hit])
     rad = np.zeros((dirs.shape[0], 3))
