@@ -38,6 +38,9 @@ def parse():
     ap.add_argument("--no-variants", action="store_true", help="FP32 only")
     ap.add_argument("--cpu-rows", type=int, default=0,
                     help="oracle sample: every k-th row (default 8)")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
+    ap.add_argument("--serve-workspace-gib", type=float, default=6.0,
+                    help="device memory for request workspaces in the serving run")
     ap.add_argument("--copy-reference", action="store_true",
                     help="also run one plain device copy of 256 MiB (the reference for "
                          "scaling hardware byte counters)")
@@ -141,15 +144,17 @@ def work_model(scene, hits, steps, dtype):
 COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "trace_hiz_kernel_c2_1080p_16spp_counters.md")
 
 
+KERNEL_SOURCES = ("device_math.h", "kernels.h", "pyramids.hip", "shade.hip")
+
+
 def kernel_sources_digest():
-    """SHA-256 over the kernel sources, in name order."""
+    """SHA-256 over the sources the kernels are compiled from, in name order."""
     import hashlib
     d = os.path.join(ROOT, "paper_2504_01358_amd", "csrc")
     h = hashlib.sha256()
-    for name in sorted(os.listdir(d)):
-        if name.endswith((".hip", ".h")):
-            with open(os.path.join(d, name), "rb") as f:
-                h.update(name.encode() + b"\0" + f.read())
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(d, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
     return h.hexdigest()
 
 
@@ -279,6 +284,103 @@ def cpu_baseline(cfg, scene, row_stride):
                        f"{busy:.1f} s compute, {wall:.1f} s wall incl. start-up")
 
 
+def _serving_scene_task(task):
+    """One (scene, resolution) of the serving mix, FP16 G-buffer bits."""
+    k, ri = task
+    os.environ["OMP_NUM_THREADS"] = "1"
+    import scenes
+    w, h = scenes.SERVE["resolutions"][ri]
+    sc = scenes.serving_scene(k, w, h)
+    bits, _ = scenes.quantise_gbuffer(sc, scenes.SERVE["dtype"])
+    return (k, ri, sc.camera, sc.depth, {b: bits[b] for b in ("normal_rough", "albedo_metal", "radiance")},
+            sc.env, sc.params)
+
+
+def serving_scenes():
+    """All scenes of the serving mix at all resolutions, generated in parallel
+    (largest first), before anything initialises the GPU."""
+    import multiprocessing as mp
+
+    import scenes
+    tasks = [(k, ri) for ri in reversed(range(len(scenes.SERVE["resolutions"])))
+             for k in range(scenes.SERVE["n_scenes"])]
+    workers = min(len(os.sched_getaffinity(0)), 8)
+    t0 = time.perf_counter()
+    with mp.get_context("spawn").Pool(workers) as pool:
+        out = list(pool.imap_unordered(_serving_scene_task, tasks))
+    return out, time.perf_counter() - t0
+
+
+def serve_run(data, workspace_bytes, dev):
+    """The serving mix through an ssr_session: requests submitted at their
+    arrival times, results collected as they finish."""
+    import torch
+
+    import scenes
+    from paper_2504_01358_amd import ssr
+    # the budget: the scenes (an upper bound of their session footprint) plus
+    # the request workspace
+    scene_bound = 0
+    for k, ri, cam, depth, bits, env, params in data:
+        px = cam["width"] * cam["height"]
+        scene_bound += px * 28 + env.size * 4 + ssr.env_mips_floats(env.shape[1], env.shape[0]) * 4 + 8 * 256
+    sess = ssr.Session(0, hbm_budget_bytes=int(scene_bound + workspace_bytes), max_slots=8,
+                       max_bypass=8)
+    ids, cams = {}, {}
+    for k, ri, cam, depth, bits, env, params in data:
+        t = {b: torch.from_numpy(bits[b].view(np.int16)).to(dev).view(torch.float16) for b in bits}
+        ids[(k, ri)] = sess.add_scene(cam, torch.from_numpy(depth).to(dev), t["normal_rough"],
+                                      t["albedo_metal"], t["radiance"], torch.from_numpy(env).to(dev))
+        cams[(k, ri)] = cam
+        base = params
+    torch.cuda.synchronize()
+    reqs = scenes.serving_requests()
+    pending, done = {}, []
+
+    def collect():
+        for tk in list(pending):
+            r = sess.poll(tk)
+            if r is not None:
+                r["rays"] = pending.pop(tk)
+                done.append(r)
+
+    t0 = time.perf_counter()
+    for n, (ta, k, ri, spp) in enumerate(reqs):
+        while time.perf_counter() - t0 < ta:
+            collect()
+            time.sleep(0.0002)
+        cam = cams[(k, ri)]
+        prm = dict(base, spp=spp, seed=7000 + n, frame=n)
+        tk, _ = sess.submit(ids[(k, ri)], prm)
+        pending[tk] = cam["width"] * cam["height"] * spp
+    for tk in list(pending):
+        r = sess.wait(tk)
+        r["rays"] = pending.pop(tk)
+        done.append(r)
+    st = sess.stats()
+    sess.close()
+    lat = np.array([r["t_done"] - r["t_submit"] for r in done]) * 1e3
+    queue = np.array([r["t_admit"] - r["t_submit"] for r in done]) * 1e3
+    span = max(r["t_done"] for r in done) - min(r["t_submit"] for r in done)
+    rays = sum(r["rays"] for r in done)
+    ev = sorted([(r["t_admit"], 1) for r in done] + [(r["t_done"], -1) for r in done])
+    conc = peak = 0
+    for _, d in ev:
+        conc += d
+        peak = max(peak, conc)
+    return {"requests": len(done), "failed": int(sum(r["status"] != 0 for r in done)),
+            "latency_ms_p50": float(np.median(lat)), "latency_ms_p99": float(np.quantile(lat, 0.99)),
+            "latency_ms_mean": float(lat.mean()),
+            "admission_wait_ms_p50": float(np.median(queue)),
+            "admission_wait_ms_p99": float(np.quantile(queue, 0.99)),
+            "value": rays / span / 1e6, "unit": "Mrays/s", "span_s": span,
+            "offered_Mrays_per_s": rays / reqs[-1][0] / 1e6,
+            "peak_concurrent": peak, "scene_bytes": st["scene_bytes"],
+            "workspace_bytes": st["arena_bytes"], "dtype": "f16",
+            "mix": "8 scenes (100-400 objects) x {640x360,1280x720,1920x1080,3840x2160}, spp "
+                   "{4,16,64}, 512 Poisson arrivals at 200/s, FP16 G-buffers, Hi-Z"}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -294,6 +396,11 @@ def main():
         cpu = cpu_baseline(args.config, scene, args.cpu_rows or 8)
         print(f"bench: oracle {cpu['value']:.3f} Mrays/s on {cpu['cores']} cores",
               file=sys.stderr, flush=True)
+
+    serve_data = None
+    if not args.no_serve:
+        serve_data, gen_s = serving_scenes()
+        print(f"bench: serving scenes generated in {gen_s:.1f} s", file=sys.stderr, flush=True)
 
     import torch
 
@@ -366,6 +473,11 @@ def main():
             line[dt] = {"value": rays / (res[dt]["ms_per_step"] * 1e-3) / 1e6,
                         "ms_per_step": res[dt]["ms_per_step"], "trace_ms": res[dt]["trace_ms"],
                         "resolve_ms": res[dt]["resolve_ms"]}
+    if serve_data is not None:
+        line["serve"] = serve_run(serve_data, int(args.serve_workspace_gib * (1 << 30)), dev)
+        print(f"bench: serve p50 {line['serve']['latency_ms_p50']:.1f} ms p99 "
+              f"{line['serve']['latency_ms_p99']:.1f} ms, {line['serve']['value']:.0f} Mrays/s",
+              file=sys.stderr, flush=True)
     if cpu is not None:
         line["cpu_baseline"] = cpu
     ctx.close()

@@ -57,7 +57,11 @@ typedef enum {
     SSR_E_DTYPE = -2,  /* unknown G-buffer storage type                          */
     SSR_E_NOMEM = -3,  /* the context's workspace could not be allocated         */
     SSR_E_HIP = -4,    /* the HIP runtime reported an error                      */
-    SSR_E_DEVICE = -5  /* no such device, or it is not a gfx950 device          */
+    SSR_E_DEVICE = -5, /* no such device, or it is not a gfx950 device          */
+    SSR_E_BUDGET = -6, /* the session's device-memory budget cannot hold it     */
+    SSR_E_BUSY = -7,   /* the session is serving (or stopping): not allowed now  */
+    SSR_E_TICKET = -8, /* no such request (never submitted, or already retired) */
+    SSR_PENDING = 1    /* the request has not finished yet                       */
 } ssr_status;
 
 /* Storage type of the three packed G-buffers (depth is always float32). */
@@ -213,6 +217,89 @@ int ssr_philox4x32_10(const uint32_t* ctr, const uint32_t* key, int64_t n, uint3
 
 /* Static description of a status code. */
 const char* ssr_status_string(int status);
+
+/* ------------------------------------------------------------------------
+ * Serving session.  Scenes (camera, G-buffer, environment) are copied once
+ * into device memory the session owns; render requests then name a scene and
+ * the per-frame parameters.  A request waits until a slot is free and the
+ * session's device-memory budget holds its workspace (depth pyramid and
+ * per-sample hit codes: ssr_session_request_bytes); admitted requests run
+ * concurrently, each on its own stream, and new requests are admitted as
+ * earlier ones finish (continuous batching).  Waiting requests are admitted
+ * oldest first; one that does not fit may be overtaken by later ones that do,
+ * at most max_bypass times.  Each result is the frame ssr_shade renders for
+ * the same scene and parameters, bit for bit, whatever else runs beside it.
+ *
+ * For callers that serve many frames from resident scenes (the persistent
+ * request loop of the method's serving use): submit and poll are
+ * thread-safe; add_scene is allowed only before the first submit.
+ * ------------------------------------------------------------------------ */
+typedef struct ssr_session ssr_session;
+
+typedef struct {
+    int64_t hbm_budget_bytes; /* device memory for scenes and request workspaces  */
+    int32_t max_slots;        /* requests on the device at once, 1..64            */
+    int32_t max_bypass;       /* times the oldest waiting request may be overtaken */
+} ssr_session_cfg;
+
+typedef struct {
+    int32_t scene_id;   /* from ssr_session_add_scene                             */
+    ssr_params params;  /* as for ssr_shade                                       */
+    float* out_rgb;     /* [H][W][3] float32 device buffer of the scene's size,
+                           caller-owned; written when the request finishes and
+                           must stay valid until poll / wait reports it        */
+} ssr_request;
+
+typedef struct {
+    int32_t status;          /* SSR_OK, or the error the request's work hit     */
+    double t_submit;         /* seconds since the session was created, host    */
+    double t_admit;          /*   monotonic clock: submitted, launched, seen    */
+    double t_done;           /*   finished by the session                       */
+    int64_t workspace_bytes; /* device memory the request held                  */
+} ssr_result;
+
+typedef struct {
+    int64_t scene_bytes;     /* device memory held by the resident scenes         */
+    int64_t arena_bytes;     /* workspace arena (0 before the first submit)        */
+    int64_t arena_used;      /* workspace held by running requests now             */
+    int32_t running;         /* requests on the device now                         */
+    int32_t waiting;         /* requests queued for admission                      */
+    int64_t completed;       /* requests finished so far                           */
+} ssr_session_stats;
+
+/* Create a session on gfx950 device `device`.  Nothing is allocated until
+ * scenes are added; the first submit reserves the rest of the budget as the
+ * workspace arena and starts the session's worker thread. */
+int ssr_session_create(int device, const ssr_session_cfg* cfg, ssr_session** out);
+
+/* Copy a scene (all device buffers, as for ssr_shade; gbuf->hiz and env->mips
+ * are ignored) into session memory and build its env mip chain, on `stream`,
+ * then wait for the copy.  The copy counts against the budget
+ * (SSR_E_BUDGET).  Only before the first submit (else SSR_E_BUSY). */
+int ssr_session_add_scene(ssr_session* s, const ssr_camera* cam, const ssr_gbuffer* gbuf,
+                          const ssr_env* env, int32_t* scene_id, void* stream);
+
+/* Device-memory workspace a request needs, in bytes (-1 if invalid). */
+int64_t ssr_session_request_bytes(ssr_session* s, const ssr_request* req);
+
+/* Queue a request; *ticket names it.  SSR_E_BUDGET if its workspace can never
+ * fit the budget left after the scenes. */
+int ssr_session_submit(ssr_session* s, const ssr_request* req, uint64_t* ticket);
+
+/* SSR_OK and *result once the request has finished (the ticket is then
+ * retired), SSR_PENDING before, SSR_E_TICKET for an unknown ticket. */
+int ssr_session_poll(ssr_session* s, uint64_t ticket, ssr_result* result);
+
+/* As poll, but blocks until the request has finished. */
+int ssr_session_wait(ssr_session* s, uint64_t ticket, ssr_result* result);
+
+/* A snapshot of the session's occupancy. */
+int ssr_session_get_stats(ssr_session* s, ssr_session_stats* out);
+
+/* Stop the session: waiting requests are dropped, running ones finish, all
+ * session memory is freed.  No other call on `s` may be in progress or
+ * follow.  NULL is accepted. */
+void ssr_session_destroy(ssr_session* s);
 
 #ifdef __cplusplus
 }

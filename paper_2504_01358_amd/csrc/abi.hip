@@ -78,6 +78,63 @@ int check_params(const ssr_params* p) {
 
 }  // namespace
 
+namespace ssr {
+
+int fill_args(const ssr_camera* cam, const ssr_gbuffer* g, const ssr_env* env, const ssr_params* p,
+              bool need_env, ShadeArgs* a, EnvLayout* env_lay, HizLayout* hiz_lay) {
+    if (!g || (need_env && !env)) return SSR_E_ARG;
+    int st = check_camera(cam);
+    if (st != SSR_OK) return st;
+    st = check_params(p);
+    if (st != SSR_OK) return st;
+    if (g->dtype != SSR_F32 && g->dtype != SSR_F16 && g->dtype != SSR_BF16) return SSR_E_DTYPE;
+    if (need_env && (!env->rgb || !make_env_layout(env->width, env->height, env_lay)))
+        return SSR_E_ARG;
+    if (cam->width == 0 || cam->height == 0) return 1;
+    if (!g->depth || !g->normal_rough || !g->albedo_metal || !g->radiance) return SSR_E_ARG;
+    // (the hierarchical march needs the pyramid; the layout also bounds W H)
+    if (!make_hiz_layout(cam->width, cam->height, hiz_lay)) return SSR_E_ARG;
+
+    memset(a, 0, sizeof(*a));
+    a->W = cam->width;
+    a->H = cam->height;
+    for (int k = 0; k < 3; ++k) {
+        a->pos[k] = cam->pos[k];
+        a->right[k] = cam->rot[k];
+        a->up[k] = cam->rot[3 + k];
+        a->fwd[k] = cam->rot[6 + k];
+    }
+    a->fx = cam->fx;
+    a->fy = cam->fy;
+    a->cx = cam->cx;
+    a->cy = cam->cy;
+    a->z_near = cam->z_near;
+    a->depth = g->depth;
+    a->normal_rough = g->normal_rough;
+    a->albedo_metal = g->albedo_metal;
+    a->radiance = g->radiance;
+    a->hiz_lay = *hiz_lay;
+    if (need_env) a->env_lay = *env_lay;
+    a->spp = p->spp;
+    a->max_steps = p->max_steps;
+    // linear march: samples t_k = k * step_len for k = 1..K, K = min(max_steps,
+    // floor(max_dist / step_len)), evaluated in double as the specification states
+    if (p->march == SSR_MARCH_LINEAR) {
+        const double k = floor(static_cast<double>(p->max_dist) / static_cast<double>(p->step_len));
+        a->linear_samples = k < static_cast<double>(p->max_steps) ? static_cast<int>(k) : p->max_steps;
+    }
+    a->step_len = p->step_len;
+    a->max_dist = p->max_dist;
+    a->thickness = p->thickness;
+    a->key0 = static_cast<uint32_t>(p->seed & 0xFFFFFFFFu);
+    a->key1 = static_cast<uint32_t>(p->seed >> 32);
+    a->frame = p->frame;
+    a->flags = p->flags;
+    return SSR_OK;
+}
+
+}  // namespace ssr
+
 extern "C" {
 
 const char* ssr_status_string(int status) {
@@ -88,6 +145,10 @@ const char* ssr_status_string(int status) {
         case SSR_E_NOMEM: return "device workspace allocation failed";
         case SSR_E_HIP: return "HIP runtime error";
         case SSR_E_DEVICE: return "no such device or not a gfx950 device";
+        case SSR_E_BUDGET: return "the session's device-memory budget cannot hold it";
+        case SSR_E_BUSY: return "not allowed while the session is serving or stopping";
+        case SSR_E_TICKET: return "no such request";
+        case SSR_PENDING: return "pending";
         default: return "unknown status";
     }
 }
@@ -183,55 +244,10 @@ namespace {
 int prepare(ssr_ctx* ctx, const ssr_camera* cam, const ssr_gbuffer* g, const ssr_env* env,
             const ssr_params* p, bool need_env, ssr::ShadeArgs* a, ssr::EnvLayout* env_lay,
             ssr::HizLayout* hiz_lay) {
-    if (!ctx || !g || (need_env && !env)) return SSR_E_ARG;
-    int st = check_camera(cam);
+    if (!ctx) return SSR_E_ARG;
+    const int st = ssr::fill_args(cam, g, need_env ? env : nullptr, p, need_env, a, env_lay, hiz_lay);
     if (st != SSR_OK) return st;
-    st = check_params(p);
-    if (st != SSR_OK) return st;
-    if (g->dtype != SSR_F32 && g->dtype != SSR_F16 && g->dtype != SSR_BF16) return SSR_E_DTYPE;
-    if (need_env && (!env->rgb || !ssr::make_env_layout(env->width, env->height, env_lay)))
-        return SSR_E_ARG;
-    if (cam->width == 0 || cam->height == 0) return 1;
-    if (!g->depth || !g->normal_rough || !g->albedo_metal || !g->radiance) return SSR_E_ARG;
-    // (the hierarchical march needs the pyramid; the layout also bounds W H)
-    if (!ssr::make_hiz_layout(cam->width, cam->height, hiz_lay)) return SSR_E_ARG;
     if (hipSetDevice(ctx->device) != hipSuccess) return SSR_E_HIP;
-
-    memset(a, 0, sizeof(*a));
-    a->W = cam->width;
-    a->H = cam->height;
-    for (int k = 0; k < 3; ++k) {
-        a->pos[k] = cam->pos[k];
-        a->right[k] = cam->rot[k];
-        a->up[k] = cam->rot[3 + k];
-        a->fwd[k] = cam->rot[6 + k];
-    }
-    a->fx = cam->fx;
-    a->fy = cam->fy;
-    a->cx = cam->cx;
-    a->cy = cam->cy;
-    a->z_near = cam->z_near;
-    a->depth = g->depth;
-    a->normal_rough = g->normal_rough;
-    a->albedo_metal = g->albedo_metal;
-    a->radiance = g->radiance;
-    a->hiz_lay = *hiz_lay;
-    if (need_env) a->env_lay = *env_lay;
-    a->spp = p->spp;
-    a->max_steps = p->max_steps;
-    // linear march: samples t_k = k * step_len for k = 1..K, K = min(max_steps,
-    // floor(max_dist / step_len)), evaluated in double as the specification states
-    if (p->march == SSR_MARCH_LINEAR) {
-        const double k = floor(static_cast<double>(p->max_dist) / static_cast<double>(p->step_len));
-        a->linear_samples = k < static_cast<double>(p->max_steps) ? static_cast<int>(k) : p->max_steps;
-    }
-    a->step_len = p->step_len;
-    a->max_dist = p->max_dist;
-    a->thickness = p->thickness;
-    a->key0 = static_cast<uint32_t>(p->seed & 0xFFFFFFFFu);
-    a->key1 = static_cast<uint32_t>(p->seed >> 32);
-    a->frame = p->frame;
-    a->flags = p->flags;
     a->tile_counter = ctx->counter;
     return SSR_OK;
 }

@@ -61,6 +61,12 @@ hipError_t launch_env_mips(const float* rgb, const EnvLayout& lay, float4* mips,
                            hipStream_t stream);
 hipError_t launch_hiz(const float* depth, const HizLayout& lay, float thickness, float4* pyramid,
                       hipStream_t stream);
+// Validate a camera, G-buffer, env (when need_env) and parameters and fill
+// `a` with everything but the workspace and output pointers.  Returns SSR_OK,
+// 1 for an empty image, or an error status.
+int fill_args(const ssr_camera* cam, const ssr_gbuffer* g, const ssr_env* env, const ssr_params* p,
+              bool need_env, ShadeArgs* a, EnvLayout* env_lay, HizLayout* hiz_lay);
+
 // Per-sample hit codes into args.codes (and iteration counts into args.steps).
 hipError_t launch_trace(const ShadeArgs& args, int dtype, int march, int cu_count,
                         hipStream_t stream);

@@ -22,7 +22,12 @@ HIT_OFFSCREEN, HIT_INVALID, HIT_BACKGROUND, HIT_CAP, HIT_SKIPPED = -1, -2, -3, -
 
 SYMBOLS = ("ssr_ctx_create", "ssr_ctx_destroy", "ssr_shade", "ssr_trace", "ssr_resolve",
            "ssr_env_mips_floats", "ssr_env_build_mips", "ssr_hiz_floats", "ssr_hiz_build",
-           "ssr_philox4x32_10", "ssr_status_string")
+           "ssr_philox4x32_10", "ssr_status_string", "ssr_session_create",
+           "ssr_session_add_scene", "ssr_session_request_bytes", "ssr_session_submit",
+           "ssr_session_poll", "ssr_session_wait", "ssr_session_get_stats",
+           "ssr_session_destroy")
+
+PENDING = 1
 
 
 class SSRError(RuntimeError):
@@ -56,6 +61,27 @@ class Params(ctypes.Structure):
                 ("frame", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
 
 
+class SessionCfg(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("max_slots", ctypes.c_int32),
+                ("max_bypass", ctypes.c_int32)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("scene_id", ctypes.c_int32), ("params", Params), ("out_rgb", ctypes.c_void_p)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("t_submit", ctypes.c_double),
+                ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double),
+                ("workspace_bytes", ctypes.c_int64)]
+
+
+class SessionStats(ctypes.Structure):
+    _fields_ = [("scene_bytes", ctypes.c_int64), ("arena_bytes", ctypes.c_int64),
+                ("arena_used", ctypes.c_int64), ("running", ctypes.c_int32),
+                ("waiting", ctypes.c_int32), ("completed", ctypes.c_int64)]
+
+
 def _load():
     if not os.path.exists(_LIB_PATH):
         raise ImportError(f"{_LIB_PATH} is missing: build it with `python -m paper_2504_01358_amd.build`")
@@ -82,6 +108,22 @@ def _load():
     lib.ssr_hiz_build.restype = ctypes.c_int
     lib.ssr_philox4x32_10.argtypes = [vp, vp, ctypes.c_int64, vp, vp]
     lib.ssr_philox4x32_10.restype = ctypes.c_int
+    lib.ssr_session_create.argtypes = [ctypes.c_int, P(SessionCfg), P(vp)]
+    lib.ssr_session_create.restype = ctypes.c_int
+    lib.ssr_session_add_scene.argtypes = [vp, P(Camera), P(GBuffer), P(Env), P(ctypes.c_int32), vp]
+    lib.ssr_session_add_scene.restype = ctypes.c_int
+    lib.ssr_session_request_bytes.argtypes = [vp, P(Request)]
+    lib.ssr_session_request_bytes.restype = ctypes.c_int64
+    lib.ssr_session_submit.argtypes = [vp, P(Request), P(ctypes.c_uint64)]
+    lib.ssr_session_submit.restype = ctypes.c_int
+    lib.ssr_session_poll.argtypes = [vp, ctypes.c_uint64, P(Result)]
+    lib.ssr_session_poll.restype = ctypes.c_int
+    lib.ssr_session_wait.argtypes = [vp, ctypes.c_uint64, P(Result)]
+    lib.ssr_session_wait.restype = ctypes.c_int
+    lib.ssr_session_get_stats.argtypes = [vp, P(SessionStats)]
+    lib.ssr_session_get_stats.restype = ctypes.c_int
+    lib.ssr_session_destroy.argtypes = [vp]
+    lib.ssr_session_destroy.restype = None
     lib.ssr_status_string.argtypes = [ctypes.c_int]
     lib.ssr_status_string.restype = ctypes.c_char_p
     return lib
@@ -254,6 +296,87 @@ class Context:
                              _stream(stream, depth.device))
         _check(st, "ssr_resolve")
         return out
+
+
+class Session:
+    """An ``ssr_session``: resident scenes and a queue of render requests that
+    the session admits by device memory and runs concurrently."""
+
+    def __init__(self, device=0, hbm_budget_bytes=8 << 30, max_slots=4, max_bypass=4):
+        self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
+        cfg = SessionCfg(int(hbm_budget_bytes), int(max_slots), int(max_bypass))
+        h = ctypes.c_void_p()
+        _check(lib.ssr_session_create(self.device.index or 0, ctypes.byref(cfg), ctypes.byref(h)),
+               "ssr_session_create")
+        self._h = h
+        self._scenes = {}    # id -> (camera, H, W)
+        self._outs = {}      # ticket -> output tensor, kept alive until retired
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib.ssr_session_destroy(self._h)
+            self._h = None
+            self._outs.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def add_scene(self, camera, depth, normal_rough, albedo_metal, radiance, env, stream=None):
+        """Copy a scene into the session; returns its id."""
+        cam = camera if isinstance(camera, Camera) else make_camera(camera)
+        g = Context._gbuf(cam, depth, normal_rough, albedo_metal, radiance, None)
+        e = Context._env(env, None)
+        sid = ctypes.c_int32()
+        _check(lib.ssr_session_add_scene(self._h, ctypes.byref(cam), ctypes.byref(g),
+                                         ctypes.byref(e), ctypes.byref(sid),
+                                         _stream(stream, depth.device)), "ssr_session_add_scene")
+        self._scenes[sid.value] = cam
+        return sid.value
+
+    def _request(self, scene_id, params, out):
+        prm = params if isinstance(params, Params) else make_params(params)
+        return Request(int(scene_id), prm, None if out is None else out.data_ptr())
+
+    def request_bytes(self, scene_id, params) -> int:
+        return int(lib.ssr_session_request_bytes(self._h, ctypes.byref(self._request(scene_id, params, None))))
+
+    def submit(self, scene_id, params, out=None):
+        """Queue a frame of scene ``scene_id``; returns (ticket, out)."""
+        if scene_id not in self._scenes:
+            raise SSRError(-1, "ssr_session_submit: unknown scene")
+        cam = self._scenes[scene_id]
+        out = Context._out(out, cam, self.device)
+        t = ctypes.c_uint64()
+        _check(lib.ssr_session_submit(self._h, ctypes.byref(self._request(scene_id, params, out)),
+                                      ctypes.byref(t)), "ssr_session_submit")
+        self._outs[t.value] = out
+        return t.value, out
+
+    def _result(self, fn, ticket):
+        r = Result()
+        st = fn(self._h, ctypes.c_uint64(ticket), ctypes.byref(r))
+        if st == PENDING:
+            return None
+        _check(st, "ssr_session_poll")
+        self._outs.pop(ticket, None)
+        return dict(status=r.status, t_submit=r.t_submit, t_admit=r.t_admit, t_done=r.t_done,
+                    workspace_bytes=r.workspace_bytes)
+
+    def poll(self, ticket):
+        """The request's result dict once finished, else None."""
+        return self._result(lib.ssr_session_poll, ticket)
+
+    def wait(self, ticket):
+        """Block until the request has finished; its result dict."""
+        return self._result(lib.ssr_session_wait, ticket)
+
+    def stats(self):
+        st = SessionStats()
+        _check(lib.ssr_session_get_stats(self._h, ctypes.byref(st)), "ssr_session_get_stats")
+        return {f: getattr(st, f) for f, _ in SessionStats._fields_}
 
 
 def env_mips_floats(width, height) -> int:

@@ -12,6 +12,7 @@ in for the rasterised G-buffers of Eq. (g-buffer) in Sec. 3.2.
 
 from .generate import (  # noqa: F401
     CONFIGS,
+    SERVE,
     Scene,
     bf16_round,
     f16_round,
@@ -19,4 +20,6 @@ from .generate import (  # noqa: F401
     make_env,
     make_scene,
     quantise_gbuffer,
+    serving_requests,
+    serving_scene,
 )

@@ -48,6 +48,36 @@ CONFIGS = {
 
 MARCH_CODES = {"linear": 0, "hiz": 1}
 
+# The serving mix: 8 resident scenes of 100-400 objects (spheres and boxes
+# in equal expectation), each rasterised at four resolutions with the same
+# objects and environment, FP16 G-buffers; 512 requests with exponential
+# inter-arrival times at 200 requests/s, resolution, scene and spp uniform.
+SERVE = dict(
+    n_scenes=8, objects=(100, 400), seed=50,
+    resolutions=((640, 360), (1280, 720), (1920, 1080), (3840, 2160)),
+    spp=(4, 16, 64), n_requests=512, rate=200.0, dtype="f16")
+
+
+def serving_scene(k, width, height) -> Scene:
+    """Scene k of the serving mix at one resolution."""
+    rng = np.random.default_rng([SERVE["seed"], k])
+    n = int(rng.integers(SERVE["objects"][0], SERVE["objects"][1] + 1))
+    n_spheres = int(rng.binomial(n, 0.5))
+    cfg = dict(CONFIGS["c2"], width=width, height=height, n_spheres=n_spheres,
+               n_boxes=n - n_spheres)
+    return make_scene(cfg, seed=SERVE["seed"] * 1000 + k)
+
+
+def serving_requests():
+    """(arrival time s, scene index, resolution index, spp) of each request."""
+    rng = np.random.default_rng([SERVE["seed"], 10 ** 6])
+    n = SERVE["n_requests"]
+    t = np.cumsum(rng.exponential(1.0 / SERVE["rate"], n))
+    sc = rng.integers(0, SERVE["n_scenes"], n)
+    res = rng.integers(0, len(SERVE["resolutions"]), n)
+    spp = rng.choice(SERVE["spp"], n)
+    return [(float(a), int(b), int(c), int(d)) for a, b, c, d in zip(t, sc, res, spp)]
+
 
 @dataclasses.dataclass
 class Scene:

@@ -36,7 +36,7 @@ def declared_functions():
 
 def test_every_declared_symbol_is_exported(lib):
     names = declared_functions()
-    assert len(names) == 11, names
+    assert len(names) == 19, names
     raw = ctypes.CDLL(LIB)
     for n in names:
         assert hasattr(raw, n), n
@@ -51,6 +51,11 @@ def test_struct_layout_matches_header(lib, tmp_path):
         "ssr_env": ["rgb", "width", "height", "mips"],
         "ssr_params": ["spp", "march", "max_steps", "step_len", "max_dist", "thickness", "seed",
                        "frame", "flags"],
+        "ssr_session_cfg": ["hbm_budget_bytes", "max_slots", "max_bypass"],
+        "ssr_request": ["scene_id", "params", "out_rgb"],
+        "ssr_result": ["status", "t_submit", "t_admit", "t_done", "workspace_bytes"],
+        "ssr_session_stats": ["scene_bytes", "arena_bytes", "arena_used", "running", "waiting",
+                              "completed"],
     }
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ssr.h"', "int main(void){"]
     for s, fs in fields.items():
@@ -67,7 +72,8 @@ def test_struct_layout_matches_header(lib, tmp_path):
             a, b, c = line.split()
             got[(a, b)] = int(c)
     py = {"ssr_camera": lib.Camera, "ssr_gbuffer": lib.GBuffer, "ssr_env": lib.Env,
-          "ssr_params": lib.Params}
+          "ssr_params": lib.Params, "ssr_session_cfg": lib.SessionCfg, "ssr_request": lib.Request,
+          "ssr_result": lib.Result, "ssr_session_stats": lib.SessionStats}
     for s, cls in py.items():
         assert got[(s, "size")] == ctypes.sizeof(cls), s
         for f in fields[s]:
@@ -115,4 +121,16 @@ def test_host_side_argument_checks(lib):
     assert raw.ssr_philox4x32_10(None, None, 5, None, None) == -1
     assert raw.ssr_philox4x32_10(None, None, -1, None, None) == -1
     assert raw.ssr_ctx_create(0, None) == -1
+    cfg = lib.SessionCfg(1 << 30, 4, 4)
+    assert raw.ssr_session_create(0, byref(cfg), None) == -1
+    h = ctypes.c_void_p()
+    for bad in (lib.SessionCfg(0, 4, 4), lib.SessionCfg(1 << 30, 0, 4), lib.SessionCfg(1 << 30, 65, 4),
+                lib.SessionCfg(1 << 30, 4, -1)):
+        assert raw.ssr_session_create(0, byref(bad), byref(h)) == -1
+    assert raw.ssr_session_submit(None, None, None) == -1
+    assert raw.ssr_session_poll(None, 1, None) == -1
+    assert raw.ssr_session_wait(None, 1, None) == -1
+    assert raw.ssr_session_request_bytes(None, None) == -1
+    assert raw.ssr_session_get_stats(None, None) == -1
+    raw.ssr_session_destroy(None)
     raw.ssr_ctx_destroy(None)
