@@ -22,8 +22,10 @@ Modules:
   env     - equirect lookup, box mip chain, bilinear/trilinear filtering
   brdf    - GGX D, Schlick F, Smith G1, VNDF sampling, sample weights
   march   - Hi-Z min pyramid, linear march, Hi-Z march, brute-force checker
-  shade   - the whole per-pixel estimator
+  shade   - the whole per-pixel estimator (optionally with given hit codes)
+  grad    - derivatives of the estimator with the hit codes held fixed,
+            by finite differences of the forward
 """
 
-from . import brdf, camera, env, march, philox, shade  # noqa: F401
+from . import brdf, camera, env, grad, march, philox, shade  # noqa: F401
 from .shade import shade_frame, shade_pixels  # noqa: F401

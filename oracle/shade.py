@@ -42,12 +42,18 @@ HIT_SKIPPED = -5
 
 
 def shade_pixels(cam, gbuf, env_rgb, params, pix, pyramid=None, mips=None,
-                 check_long_form=True, sensitivity=None):
+                 check_long_form=True, sensitivity=None, replay_hits=None):
     """Shade the flat pixel indices ``pix``.
 
     ``gbuf``: dict with ``depth`` [H][W], ``normal_rough``, ``albedo_metal``,
     ``radiance`` [H][W][4] (any float dtype; widened to float64).
     Returns dict(out [n][3], hits [n][S], steps [n][S]).
+
+    With ``replay_hits`` [n][S] (hit codes, as this function returns them) the march
+    is not run: each valid sample reads the radiance its given code names.
+    This is the estimator with the hit selection held fixed, the form whose
+    derivatives the adjoint computes (the march itself is not
+    differentiable).
 
     With ``sensitivity=eps`` (radians) the result also holds ``bound`` [n][3]:
     how far each output can move when every direction the estimator looks up
@@ -67,7 +73,7 @@ def shade_pixels(cam, gbuf, env_rgb, params, pix, pyramid=None, mips=None,
     rad = np.asarray(gbuf["radiance"], np.float64).reshape(-1, 4)
     if mips is None:
         mips = env.build_mips(env_rgb)
-    if pyramid is None and int(params["march"]) == 1:
+    if pyramid is None and int(params["march"]) == 1 and replay_hits is None:
         pyramid = (march.hiz_pyramid(depth), march.hiz_max_pyramid(depth))
 
     i = pix % W
@@ -142,18 +148,24 @@ def shade_pixels(cam, gbuf, env_rgb, params, pix, pyramid=None, mips=None,
     code = np.full(rep.shape[0], HIT_INVALID, np.int64)
     nit = np.zeros(rep.shape[0], np.int64)
     r_ok = np.nonzero(ok)[0]
-    org = np.stack([i[fg][rep[r_ok]], j[fg][rep[r_ok]]], axis=1)
-    Dv = camera.world_to_view_dir(c, l[r_ok])
-    V0r = V0[rep[r_ok]]
-    if int(params["march"]) == 0:
-        cc, it = march.march_linear(cam, depth, org, V0r, Dv, float(params["step_len"]),
-                                    int(params["max_steps"]), float(params["max_dist"]),
-                                    float(params["thickness"]))
+    if replay_hits is not None:
+        given = np.asarray(replay_hits, np.int64).reshape(n, S)[pf].reshape(-1)
+        code[r_ok] = given[r_ok]
+        # a replayed code only counts where the sample is valid here too
+        ok &= (code >= 0) | (code == march.HIT_OFFSCREEN) | (code == march.HIT_CAP)
     else:
-        cc, it = march.march_hiz(cam, pyramid, org, V0r, Dv, int(params["max_steps"]),
-                                 float(params["max_dist"]), float(params["thickness"]))
-    code[r_ok] = cc
-    nit[r_ok] = it
+        org = np.stack([i[fg][rep[r_ok]], j[fg][rep[r_ok]]], axis=1)
+        Dv = camera.world_to_view_dir(c, l[r_ok])
+        V0r = V0[rep[r_ok]]
+        if int(params["march"]) == 0:
+            cc, it = march.march_linear(cam, depth, org, V0r, Dv, float(params["step_len"]),
+                                        int(params["max_steps"]), float(params["max_dist"]),
+                                        float(params["thickness"]))
+        else:
+            cc, it = march.march_hiz(cam, pyramid, org, V0r, Dv, int(params["max_steps"]),
+                                     float(params["max_dist"]), float(params["thickness"]))
+        code[r_ok] = cc
+        nit[r_ok] = it
 
     # radiance along each valid ray: c1 at the hit pixel, else the environment
     L = np.zeros((rep.shape[0], 3))

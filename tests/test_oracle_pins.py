@@ -441,3 +441,107 @@ def test_background_reads_environment():
     d = camera.view_ray_dir(c, ii.reshape(-1), jj.reshape(-1))
     assert np.allclose(r["out"].reshape(-1, 3), env.bilinear(envmap, d), rtol=1e-14)
     assert np.all(r["hits"] == shade.HIT_BACKGROUND)
+
+
+# ------------------------------------------------- derivatives (fixed hits) --
+
+def _small_scene(w=24, h=16, spp=4, seed=5):
+    import scenes
+    sc = scenes.make_scene("c2", seed=seed, width=w, height=h, spp=spp)
+    g = dict(depth=sc.depth, normal_rough=sc.normal_rough, albedo_metal=sc.albedo_metal,
+             radiance=sc.radiance)
+    return sc, g
+
+
+def test_replaying_hits_reproduces_the_forward():
+    sc, g = _small_scene()
+    pix = np.arange(sc.width * sc.height)
+    a = shade.shade_pixels(sc.camera, g, sc.env, sc.params, pix)
+    b = shade.shade_pixels(sc.camera, g, sc.env, sc.params, pix, replay_hits=a["hits"])
+    assert np.array_equal(a["out"], b["out"]) and np.array_equal(a["hits"], b["hits"])
+
+
+def test_pixel_gradients_closed_form_in_a_furnace():
+    """Uniform environment (L per channel), specular off: out = (1 - m) a L,
+    so d/da_c = (1 - m) L_c g_c, d/dm = -sum_c g_c a_c L_c and the normal and
+    roughness derivatives vanish."""
+    from oracle import grad
+    Lc = np.array([1.5, 0.7, 2.2])
+    cam, g = open_floor(w=12, h=8, metal=0.3, rough=0.4)
+    rng = np.random.default_rng(4)
+    g["albedo_metal"][..., :3] = rng.uniform(0, 1, g["albedo_metal"][..., :3].shape)
+    g["albedo_metal"][..., 3] = rng.uniform(0.1, 0.9, g["albedo_metal"][..., 3].shape)
+    g["normal_rough"][..., 3] = rng.uniform(0.1, 0.9, g["normal_rough"][..., 3].shape)
+    envmap = np.broadcast_to(Lc, (8, 16, 3)).copy()
+    params = dict(spp=2, march=1, max_steps=64, step_len=0.125, max_dist=100.0,
+                  thickness=0.05, seed=1, frame=0, flags=shade.NO_SPECULAR)
+    pix = np.arange(12 * 8)
+    hits = np.full((pix.size, 2), shade.HIT_SKIPPED)
+    g_out = rng.normal(size=(pix.size, 3))
+    d = grad.pixel_grads(cam, g, envmap, params, pix, hits, g_out)
+    am = g["albedo_metal"].reshape(-1, 4)
+    assert np.allclose(d[:, 4:7], (1 - am[:, 3:4]) * Lc * g_out, atol=1e-8)
+    assert np.allclose(d[:, 7], -(g_out * am[:, :3] * Lc).sum(1), atol=1e-8)
+    assert np.abs(d[:, :4]).max() < 1e-8
+
+
+def test_pixel_gradients_converge_with_the_step():
+    """Central differences at eps and eps/4 agree: the fixed-hit estimator is
+    smooth in every per-pixel input (up to the kinks of bilinear filtering at
+    texel boundaries, kept small here by a smoothly varying map)."""
+    from oracle import grad
+    sc, g = _small_scene(w=12, h=8, spp=4)
+    he, we = sc.env.shape[:2]
+    yy, xx = np.meshgrid(np.arange(he), np.arange(we), indexing="ij")
+    smooth = 1.0 + 0.5 * np.sin(2 * np.pi * xx / we)[..., None] * np.cos(np.pi * yy / he)[..., None] \
+        * np.array([1.0, 0.5, -0.7])
+    pix = np.arange(12 * 8)
+    hits = shade.shade_pixels(sc.camera, g, smooth, sc.params, pix)["hits"]
+    g_out = np.random.default_rng(1).normal(size=(pix.size, 3))
+    a = grad.pixel_grads(sc.camera, g, smooth, sc.params, pix, hits, g_out, eps=1e-6)
+    b = grad.pixel_grads(sc.camera, g, smooth, sc.params, pix, hits, g_out, eps=2.5e-7)
+    scale = np.abs(b).max(axis=0) + 1e-12
+    assert (np.abs(a - b) / scale).max() < 1e-6
+    assert np.abs(b[:, :4]).max() > 0          # normal / roughness really matter here
+
+
+def test_env_gradients_sum_to_the_diffuse_weight():
+    """Specular off: the trilinear weights sum to one over the texels of every
+    level and each mip texel is a block mean, so the derivative summed over
+    all texels of channel c is sum_p g_pc (1 - m_p) a_pc over surface pixels
+    plus sum_p g_pc over background pixels (which show the map itself)."""
+    from oracle import grad
+    sc, g = _small_scene(w=10, h=6, spp=1)
+    envmap = np.random.default_rng(3).uniform(0.5, 2.0, (4, 8, 3))
+    params = dict(sc.params, flags=shade.NO_SPECULAR)
+    hits = np.full((6, 10, 1), shade.HIT_SKIPPED)
+    g_out = np.random.default_rng(2).normal(size=(6, 10, 3))
+    tex = [(y, x, c) for y in range(4) for x in range(8) for c in range(3)]
+    d = grad.env_grads(sc.camera, g, envmap, params, hits, g_out, tex).reshape(4, 8, 3)
+    am = np.asarray(g["albedo_metal"], np.float64)
+    fg = np.isfinite(np.asarray(g["depth"]))
+    want = (g_out * (1 - am[..., 3:4]) * am[..., :3])[fg].sum(0) + g_out[~fg].sum(0)
+    assert (~fg).any() and fg.any()
+    assert np.allclose(d.sum(axis=(0, 1)), want, rtol=1e-9, atol=1e-9)
+
+
+def test_radiance_gradients_match_a_direct_difference():
+    from oracle import grad
+    sc, g = _small_scene(w=16, h=10, spp=4, seed=8)
+    pix = np.arange(16 * 10)
+    r = shade.shade_pixels(sc.camera, g, sc.env, sc.params, pix)
+    hits = r["hits"].reshape(10, 16, 4)
+    g_out = np.random.default_rng(6).normal(size=(10, 16, 3))
+    d = grad.radiance_grads(sc.camera, g, sc.env, sc.params, hits, g_out)
+    q = int(np.bincount(hits[hits >= 0]).argmax())          # the most-hit pixel
+    for c in range(3):
+        gg = {k: np.array(v, np.float64) for k, v in g.items()}
+        vals = []
+        for sgn in (1, -1):
+            rad = gg["radiance"].copy().reshape(-1, 4)
+            rad[q, c] += sgn * 1e-3
+            o = shade.shade_pixels(sc.camera, dict(gg, radiance=rad.reshape(10, 16, 4)), sc.env,
+                                   sc.params, pix, replay_hits=hits.reshape(-1, 4))["out"]
+            vals.append((o * g_out.reshape(-1, 3)).sum())
+        assert abs((vals[0] - vals[1]) / 2e-3 - d.reshape(-1, 3)[q, c]) < 1e-8
+    assert np.abs(d).sum() > 0
