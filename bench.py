@@ -144,7 +144,7 @@ def work_model(scene, hits, steps, dtype):
 COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "trace_hiz_kernel_c2_1080p_16spp_counters.md")
 
 
-KERNEL_SOURCES = ("device_math.h", "kernels.h", "pyramids.hip", "shade.hip")
+KERNEL_SOURCES = ("device_math.h", "kernels.h", "pyramids.hip", "shade.hip", "shading.h")
 
 
 def kernel_sources_digest():

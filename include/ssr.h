@@ -174,6 +174,32 @@ int ssr_resolve(ssr_ctx* ctx, const ssr_camera* cam, const ssr_gbuffer* gbuf,
                 const ssr_env* env, const ssr_params* params, const int32_t* hits,
                 float* out_rgb, void* stream);
 
+/* The adjoint of ssr_resolve (the shading with the hit selection held fixed;
+ * the paper differentiates its shading with the screen-space tracing treated
+ * as a fixed selection): given the hit codes `hits` [H][W][spp] of a frame and
+ * the gradient of a loss with respect to its image, grad_rgb [H][W][3], write
+ * or accumulate the gradient with respect to the inputs:
+ *   g_normal_rough [H][W][4]: written, d/d(n.x, n.y, n.z, rho) of the stored
+ *                  values (n before normalisation; rho 0 outside [0, 1]);
+ *   g_albedo_metal [H][W][4]: written, d/d(a.r, a.g, a.b, m) (m 0 outside
+ *                  [0, 1]); zero for background pixels;
+ *   g_env          [He][We][3]: ADDED to, d/d of every level-0 texel of the
+ *                  map (through the mip chain of the direct term, the
+ *                  environment read by rays that miss, and the background);
+ *   g_radiance     [H][W][4]: channels 0..2 ADDED to, d/d first-pass
+ *                  radiance of each hit pixel; channel 3 untouched.
+ * Each output may be NULL.  Derivatives flow through the sampled directions
+ * (visible-normal sample, reflection), Fresnel, masking, the roughness mip
+ * level and the bilinear weights of every environment lookup; a bilinear
+ * lookup is differentiated inside its texel cell, so the derivative is
+ * discontinuous across texel boundaries, as the function's is.  Codes
+ * outside [SSR_HIT_SKIPPED, W H) count as SSR_HIT_INVALID.  Other arguments
+ * and errors as ssr_shade. */
+int ssr_shade_backward(ssr_ctx* ctx, const ssr_camera* cam, const ssr_gbuffer* gbuf,
+                       const ssr_env* env, const ssr_params* params, const int32_t* hits,
+                       const float* grad_rgb, float* g_normal_rough, float* g_albedo_metal,
+                       float* g_env, float* g_radiance, void* stream);
+
 /* Number of floats of the env mip-chain buffer for a We x He map (0 if the
  * dimensions are invalid). */
 int64_t ssr_env_mips_floats(int32_t width, int32_t height);

@@ -20,6 +20,8 @@ struct ssr_ctx {
     int32_t* codes;
     int64_t codes_cap;  // int32
     int* counter;
+    float4* g_mips;     // adjoint: environment derivatives per mip texel
+    int64_t g_mips_cap;
 };
 
 namespace {
@@ -175,6 +177,8 @@ int ssr_ctx_create(int device, ssr_ctx** out) {
     c->codes = nullptr;
     c->codes_cap = 0;
     c->counter = nullptr;
+    c->g_mips = nullptr;
+    c->g_mips_cap = 0;
     if (hipSetDevice(device) != hipSuccess ||
         hipMalloc(reinterpret_cast<void**>(&c->counter), 256) != hipSuccess) {
         (void)hipGetLastError();
@@ -193,6 +197,7 @@ void ssr_ctx_destroy(ssr_ctx* ctx) {
         if (ctx->mips) (void)hipFree(ctx->mips);
         if (ctx->codes) (void)hipFree(ctx->codes);
         if (ctx->counter) (void)hipFree(ctx->counter);
+        if (ctx->g_mips) (void)hipFree(ctx->g_mips);
     }
     delete ctx;
 }
@@ -311,6 +316,26 @@ int ssr_resolve(ssr_ctx* ctx, const ssr_camera* cam, const ssr_gbuffer* g, const
     a.codes = const_cast<int32_t*>(hits);  // read only by the resolve kernel
     a.out = out_rgb;
     return hip_status(ssr::launch_resolve(a, g->dtype, s));
+}
+
+int ssr_shade_backward(ssr_ctx* ctx, const ssr_camera* cam, const ssr_gbuffer* g,
+                       const ssr_env* env, const ssr_params* p, const int32_t* hits,
+                       const float* grad_rgb, float* g_normal_rough, float* g_albedo_metal,
+                       float* g_env, float* g_radiance, void* stream) {
+    ssr::ShadeArgs a;
+    ssr::EnvLayout env_lay;
+    ssr::HizLayout hiz_lay;
+    int st = prepare(ctx, cam, g, env, p, true, &a, &env_lay, &hiz_lay);
+    if (st != SSR_OK) return st == 1 ? SSR_OK : st;
+    if (!hits || !grad_rgb) return SSR_E_ARG;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    st = env_mips(ctx, env, env_lay, s, &a.env);
+    if (st != SSR_OK) return st;
+    st = ensure(&ctx->g_mips, &ctx->g_mips_cap, env_lay.total);
+    if (st != SSR_OK) return st;
+    ssr::BackwardBuffers b{hits, grad_rgb, g_normal_rough, g_albedo_metal, g_env, g_radiance,
+                           ctx->g_mips};
+    return hip_status(ssr::launch_backward(a, b, g->dtype, s));
 }
 
 int ssr_shade(ssr_ctx* ctx, const ssr_camera* cam, const ssr_gbuffer* g, const ssr_env* env,

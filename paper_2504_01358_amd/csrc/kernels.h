@@ -72,6 +72,19 @@ hipError_t launch_trace(const ShadeArgs& args, int dtype, int march, int cu_coun
                         hipStream_t stream);
 // The image from the hit codes in args.codes.
 hipError_t launch_resolve(const ShadeArgs& args, int dtype, hipStream_t stream);
+
+// Buffers of the adjoint (see ssr_shade_backward).
+struct BackwardBuffers {
+    const int32_t* hits;
+    const float* grad_rgb;
+    float* g_normal_rough;
+    float* g_albedo_metal;
+    float* g_env;
+    float* g_radiance;
+    float4* g_mips;           // workspace: one texel per env mip texel
+};
+hipError_t launch_backward(const ShadeArgs& args, const BackwardBuffers& bufs, int dtype,
+                           hipStream_t stream);
 hipError_t launch_philox(const uint32_t* ctr, const uint32_t* key, int64_t n, uint32_t* out,
                          hipStream_t stream);
 

@@ -14,58 +14,9 @@
 // point (linear) or a pixel crossing (hierarchical) hits when the ray lies in
 // the slab [D, D + thickness] behind the depth buffer after having been in
 // front of it at some earlier point outside the origin pixel.
-#include <hip/hip_fp16.h>
-
-#include "device_math.h"
-#include "kernels.h"
+#include "shading.h"
 
 namespace ssr {
-
-// -------------------------------------------------------- G-buffer loads --
-
-template <int DT>
-struct Texel4;
-
-template <>
-struct Texel4<0> {  // float32
-    __device__ static float4 load(const void* p, int64_t i) {
-        return reinterpret_cast<const float4*>(p)[i];
-    }
-};
-
-template <>
-struct Texel4<1> {  // float16
-    __device__ static float4 load(const void* p, int64_t i) {
-        const ushort4 b = reinterpret_cast<const ushort4*>(p)[i];
-        return make_float4(__half2float(__ushort_as_half(b.x)), __half2float(__ushort_as_half(b.y)),
-                           __half2float(__ushort_as_half(b.z)), __half2float(__ushort_as_half(b.w)));
-    }
-};
-
-template <>
-struct Texel4<2> {  // bfloat16: the high half of a float32
-    __device__ static float4 load(const void* p, int64_t i) {
-        const ushort4 b = reinterpret_cast<const ushort4*>(p)[i];
-        return make_float4(__uint_as_float(static_cast<uint32_t>(b.x) << 16),
-                           __uint_as_float(static_cast<uint32_t>(b.y) << 16),
-                           __uint_as_float(static_cast<uint32_t>(b.z) << 16),
-                           __uint_as_float(static_cast<uint32_t>(b.w) << 16));
-    }
-};
-
-__device__ __forceinline__ EnvLevel env_level(const ShadeArgs& a, int k) {
-    return EnvLevel{a.env + a.env_lay.offset[k], a.env_lay.w[k], a.env_lay.h[k]};
-}
-
-__device__ __forceinline__ V3 view_to_world(const ShadeArgs& a, float X, float Y, float Z) {
-    return v3(X * a.right[0] + Y * a.up[0] + Z * a.fwd[0], X * a.right[1] + Y * a.up[1] + Z * a.fwd[1],
-              X * a.right[2] + Y * a.up[2] + Z * a.fwd[2]);
-}
-
-__device__ __forceinline__ V3 world_to_view(const ShadeArgs& a, V3 l) {
-    return v3(dot(l, v3(a.right[0], a.right[1], a.right[2])), dot(l, v3(a.up[0], a.up[1], a.up[2])),
-              dot(l, v3(a.fwd[0], a.fwd[1], a.fwd[2])));
-}
 
 // ---------------------------------------------------------- linear march --
 
@@ -249,141 +200,6 @@ __device__ __forceinline__ bool hiz_step(const ShadeArgs& a, const int2* lvl, Hi
     return hit | leave | (r.it >= a.max_steps);
 }
 
-// ------------------------------------------------------------ per pixel --
-
-struct Pixel {
-    bool bg;              // background (depth not finite)
-    float D, X0, Y0;      // view-space point of the pixel centre
-    V3 wo, n;             // toward the camera; shading normal
-    float rho, m;
-    V3 alb, f0;
-    float cos_no;
-    bool trace;           // specular samples are drawn
-    V3 t, b, ws;          // tangent frame; stretched view vector (visible normals)
-};
-
-template <int DT>
-__device__ __forceinline__ Pixel setup_pixel(const ShadeArgs& a, int i, int j, int64_t q) {
-    Pixel P;
-    P.D = a.depth[q];
-    P.bg = !(P.D < INFINITY);
-    const float D = P.bg ? 1.0f : P.D;
-    const float4 nr = Texel4<DT>::load(a.normal_rough, q);
-    const float4 am = Texel4<DT>::load(a.albedo_metal, q);
-    P.X0 = (static_cast<float>(i) + 0.5f - a.cx) * D / a.fx;
-    P.Y0 = -(static_cast<float>(j) + 0.5f - a.cy) * D / a.fy;
-    P.wo = -1.0f * normalize(view_to_world(a, P.X0, P.Y0, D));
-    P.n = normalize(v3(nr.x, nr.y, nr.z));
-    P.rho = fminf(fmaxf(nr.w, 0.0f), 1.0f);
-    P.m = fminf(fmaxf(am.w, 0.0f), 1.0f);
-    P.alb = v3(am.x, am.y, am.z);
-    P.f0 = v3(0.04f * (1.0f - P.m) + P.alb.x * P.m, 0.04f * (1.0f - P.m) + P.alb.y * P.m,
-              0.04f * (1.0f - P.m) + P.alb.z * P.m);
-    P.cos_no = dot(P.n, P.wo);
-    P.trace = !P.bg && !(a.flags & SSR_NO_SPECULAR) && P.cos_no > 0.0f;
-    onb(P.n, P.t, P.b);
-    const V3 wl = v3(dot(P.wo, P.t), dot(P.wo, P.b), P.cos_no);
-    // visible-normal sampling (Dupuy & Benyoub 2023): stretched view vector
-    P.ws = normalize(v3(P.rho * wl.x, P.rho * wl.y, wl.z));
-    return P;
-}
-
-// Direct diffuse c_d = (1 - m) a E_lambda(n), or the environment seen directly
-// for a background pixel.
-__device__ __forceinline__ float3 direct_term(const ShadeArgs& a, const Pixel& P, int i, int j) {
-    if (P.bg) {
-        const V3 d = normalize(view_to_world(a, (static_cast<float>(i) + 0.5f - a.cx) / a.fx,
-                                             -(static_cast<float>(j) + 0.5f - a.cy) / a.fy, 1.0f));
-        return env_bilinear(env_level(a, 0), env_angles(d));
-    }
-    if (a.flags & SSR_NO_DIRECT) return make_float3(0.0f, 0.0f, 0.0f);
-    const int top = a.env_lay.levels - 1;
-    // lambda = log2(1 + rho) * lambda_max, via log1p (no rounding of 1 + rho)
-    const float lam = fminf(fmaxf(log1pf(P.rho) * (static_cast<float>(top) * 1.44269504f), 0.0f),
-                            static_cast<float>(top));
-    const int k0 = static_cast<int>(floorf(lam));
-    const int k1 = min(k0 + 1, top);
-    const float t = lam - static_cast<float>(k0);
-    const EnvAngles ang = env_angles(P.n);
-    const float3 e0 = env_bilinear(env_level(a, k0), ang);
-    float3 e = e0;
-    if (t > 0.0f) {
-        const float3 e1 = env_bilinear(env_level(a, k1), ang);
-        e = make_float3((1.0f - t) * e0.x + t * e1.x, (1.0f - t) * e0.y + t * e1.y,
-                        (1.0f - t) * e0.z + t * e1.z);
-    }
-    const float k = 1.0f - P.m;
-    return make_float3(k * P.alb.x * e.x, k * P.alb.y * e.y, k * P.alb.z * e.z);
-}
-
-// ----------------------------------------------------------- per sample --
-
-struct SampleDir {
-    V3 l;         // reflected ray direction (world)
-    float cos_oh, cos_nl;
-};
-
-// Sample s of pixel q: Philox4x32-10 at counter (q, s, frame, 0) gives u1
-// (azimuth) and u2 (cap height) of a visible-normal sample h; l reflects wo
-// about h.
-__device__ __forceinline__ SampleDir sample_dir(const ShadeArgs& a, const Pixel& P, int64_t q,
-                                                int s) {
-    const uint4 x = philox4x32_10(
-        make_uint4(static_cast<uint32_t>(q), static_cast<uint32_t>(s), a.frame, 0u), a.key0, a.key1);
-    const float u1 = unit24(x.x), u2 = unit24(x.y);
-    // point on the spherical cap z > -ws.z: azimuth 2 pi u1, height from u2.
-    // h_std.z = z + ws.z = (1 - u2)(1 + ws.z) and 1 - z^2 = (1 - z)(1 + z) with
-    // 1 - z = u2 (1 + ws.z), 1 + z = (1 - u2)(1 + ws.z) + (1 - ws.z): no cancellation.
-    float sphi, cphi;
-    sincospif(2.0f * u1, &sphi, &cphi);
-    const float one_m_u2 = 1.0f - u2;
-    const float opz = 1.0f + P.ws.z;
-    const float hz = one_m_u2 * opz;
-    const float sin2 = (u2 * opz) * (hz + (1.0f - P.ws.z));
-    const float st = sqrtf(fmaxf(sin2, 0.0f));
-    const V3 hl = normalize(v3(P.rho * (st * cphi + P.ws.x), P.rho * (st * sphi + P.ws.y), hz));
-    const V3 h = v3(hl.x * P.t.x + hl.y * P.b.x + hl.z * P.n.x,
-                    hl.x * P.t.y + hl.y * P.b.y + hl.z * P.n.y,
-                    hl.x * P.t.z + hl.y * P.b.z + hl.z * P.n.z);
-    SampleDir d;
-    d.cos_oh = dot(P.wo, h);
-    d.l = (2.0f * d.cos_oh) * h - P.wo;
-    d.cos_nl = dot(P.n, d.l);
-    return d;
-}
-
-// Weight F(wo.h) G1(n.l) times the radiance found (c1 at a hit pixel, the
-// unfiltered environment otherwise), Kahan-accumulated per channel.
-template <int DT>
-__device__ __forceinline__ void accumulate(const ShadeArgs& a, const Pixel& P, const SampleDir& d,
-                                           int code, float* sum, float* cmp) {
-    float3 Lr;
-    if (code >= 0) {
-        const float4 c1 = Texel4<DT>::load(a.radiance, code);
-        Lr = make_float3(c1.x, c1.y, c1.z);
-    } else {
-        Lr = env_bilinear(env_level(a, 0), env_angles(d.l));
-    }
-    const float fc = 1.0f - d.cos_oh;
-    const float fc2 = fc * fc;
-    const float fr = fc2 * fc2 * fc;
-    const float g1 = smith_g1(fmaxf(d.cos_nl, 0.0f), P.rho * P.rho);
-    kahan_add(sum[0], cmp[0], (P.f0.x + (1.0f - P.f0.x) * fr) * g1 * Lr.x);
-    kahan_add(sum[1], cmp[1], (P.f0.y + (1.0f - P.f0.y) * fr) * g1 * Lr.y);
-    kahan_add(sum[2], cmp[2], (P.f0.z + (1.0f - P.f0.z) * fr) * g1 * Lr.z);
-}
-
-__device__ __forceinline__ int fill_code(const ShadeArgs& a, const Pixel& P) {
-    return P.bg ? SSR_HIT_BACKGROUND
-                : ((a.flags & SSR_NO_SPECULAR) ? SSR_HIT_SKIPPED : SSR_HIT_INVALID);
-}
-
-__device__ __forceinline__ void write_out(const ShadeArgs& a, int64_t q, float3 cd, const float* sum) {
-    const float invS = 1.0f / static_cast<float>(a.spp);
-    // one 12-byte store per pixel: a row of lanes writes one contiguous run
-    reinterpret_cast<float3*>(a.out)[q] =
-        make_float3(cd.x + sum[0] * invS, cd.y + sum[1] * invS, cd.z + sum[2] * invS);
-}
 
 // ------------------------------------------------------ linear-march trace --
 //

@@ -21,6 +21,7 @@ NO_DIRECT, NO_SPECULAR = 1, 2
 HIT_OFFSCREEN, HIT_INVALID, HIT_BACKGROUND, HIT_CAP, HIT_SKIPPED = -1, -2, -3, -4, -5
 
 SYMBOLS = ("ssr_ctx_create", "ssr_ctx_destroy", "ssr_shade", "ssr_trace", "ssr_resolve",
+           "ssr_shade_backward",
            "ssr_env_mips_floats", "ssr_env_build_mips", "ssr_hiz_floats", "ssr_hiz_build",
            "ssr_philox4x32_10", "ssr_status_string", "ssr_session_create",
            "ssr_session_add_scene", "ssr_session_request_bytes", "ssr_session_submit",
@@ -98,6 +99,9 @@ def _load():
     lib.ssr_trace.restype = ctypes.c_int
     lib.ssr_resolve.argtypes = [vp, P(Camera), P(GBuffer), P(Env), P(Params), vp, vp, vp]
     lib.ssr_resolve.restype = ctypes.c_int
+    lib.ssr_shade_backward.argtypes = [vp, P(Camera), P(GBuffer), P(Env), P(Params), vp, vp, vp,
+                                       vp, vp, vp, vp]
+    lib.ssr_shade_backward.restype = ctypes.c_int
     lib.ssr_env_mips_floats.argtypes = [ctypes.c_int32, ctypes.c_int32]
     lib.ssr_env_mips_floats.restype = ctypes.c_int64
     lib.ssr_env_build_mips.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, vp, vp]
@@ -296,6 +300,35 @@ class Context:
                              _stream(stream, depth.device))
         _check(st, "ssr_resolve")
         return out
+
+
+def _shade_backward(self, camera, depth, normal_rough, albedo_metal, radiance, env, params, hits,
+                    grad_rgb, env_mips=None, g_normal_rough=None, g_albedo_metal=None, g_env=None,
+                    g_radiance=None, stream=None):
+    """The adjoint of ``resolve`` (hit codes ``hits`` held fixed) for the image
+    gradient ``grad_rgb`` [H][W][3]: writes ``g_normal_rough`` and
+    ``g_albedo_metal`` ([H][W][4] float32) and adds to ``g_env`` ([He][We][3])
+    and ``g_radiance`` ([H][W][4]), each optional."""
+    cam = camera if isinstance(camera, Camera) else make_camera(camera)
+    prm = params if isinstance(params, Params) else make_params(params)
+    g = Context._gbuf(cam, depth, normal_rough, albedo_metal, radiance, None)
+    e = Context._env(env, env_mips)
+    H, W = cam.height, cam.width
+    _dev_tensor(hits, "hits", torch.int32, (H, W, prm.spp))
+    _dev_tensor(grad_rgb, "grad_rgb", torch.float32, (H, W, 3))
+    for name, t, shape in (("g_normal_rough", g_normal_rough, (H, W, 4)),
+                           ("g_albedo_metal", g_albedo_metal, (H, W, 4)),
+                           ("g_env", g_env, tuple(env.shape)), ("g_radiance", g_radiance, (H, W, 4))):
+        if t is not None:
+            _dev_tensor(t, name, torch.float32, shape)
+    st = lib.ssr_shade_backward(self._h, ctypes.byref(cam), ctypes.byref(g), ctypes.byref(e),
+                                ctypes.byref(prm), _ptr(hits), _ptr(grad_rgb), _ptr(g_normal_rough),
+                                _ptr(g_albedo_metal), _ptr(g_env), _ptr(g_radiance),
+                                _stream(stream, depth.device))
+    _check(st, "ssr_shade_backward")
+
+
+Context.shade_backward = _shade_backward
 
 
 class Session:
