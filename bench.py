@@ -39,6 +39,7 @@ def parse():
     ap.add_argument("--cpu-rows", type=int, default=0,
                     help="oracle sample: every k-th row (default 8)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
+    ap.add_argument("--no-backward", action="store_true", help="skip the adjoint timing")
     ap.add_argument("--serve-workspace-gib", type=float, default=6.0,
                     help="device memory for request workspaces in the serving run")
     ap.add_argument("--copy-reference", action="store_true",
@@ -284,6 +285,50 @@ def cpu_baseline(cfg, scene, row_stride):
                        f"{busy:.1f} s compute, {wall:.1f} s wall incl. start-up")
 
 
+def time_backward(ctx, dev, reps=20):
+    """The differentiation workload (800x800, 8 spp, Hi-Z, FP32): one
+    forward with hit codes, then the adjoint with every gradient output."""
+    import torch
+
+    import scenes
+    sc = scenes.make_scene("c4")
+    t = {k: torch.from_numpy(getattr(sc, k)).to(dev)
+         for k in ("depth", "normal_rough", "albedo_metal", "radiance", "env")}
+    H, W = sc.height, sc.width
+    hits = torch.empty((H, W, sc.params["spp"]), dtype=torch.int32, device=dev)
+    g_rgb = torch.randn((H, W, 3), dtype=torch.float32, device=dev)
+    g_nr = torch.empty((H, W, 4), dtype=torch.float32, device=dev)
+    g_am = torch.empty_like(g_nr)
+    g_rad = torch.zeros_like(g_nr)
+    g_env = torch.zeros_like(t["env"])
+    stream = torch.cuda.current_stream(dev)
+    args = (sc.camera, t["depth"], t["normal_rough"], t["albedo_metal"], t["radiance"], t["env"],
+            sc.params)
+
+    def fwd():
+        ctx.shade(*args, hits=hits, stream=stream)
+
+    def bwd():
+        ctx.shade_backward(*args, hits, g_rgb, g_normal_rough=g_nr, g_albedo_metal=g_am,
+                           g_env=g_env, g_radiance=g_rad, stream=stream)
+    res = {}
+    for name, fn in (("forward_ms", fwd), ("backward_ms", bwd)):
+        for _ in range(3):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        res[name] = e0.elapsed_time(e1) / reps
+    res["backward_Mpixels_per_s"] = H * W / (res["backward_ms"] * 1e-3) / 1e6
+    res["workload"] = ("c4: 800x800, 8 spp, Hi-Z, FP32; gradients for normal, roughness, albedo, "
+                       "metallic, radiance and the 256x128 env (hit codes held fixed)")
+    return res
+
+
 def _serving_scene_task(task):
     """One (scene, resolution) of the serving mix, FP16 G-buffer bits."""
     k, ri = task
@@ -473,6 +518,10 @@ def main():
             line[dt] = {"value": rays / (res[dt]["ms_per_step"] * 1e-3) / 1e6,
                         "ms_per_step": res[dt]["ms_per_step"], "trace_ms": res[dt]["trace_ms"],
                         "resolve_ms": res[dt]["resolve_ms"]}
+    if not args.no_backward:
+        line["backward"] = time_backward(ctx, dev)
+        print(f"bench: backward {line['backward']['backward_ms']:.3f} ms at 800x800 8 spp",
+              file=sys.stderr, flush=True)
     if serve_data is not None:
         line["serve"] = serve_run(serve_data, int(args.serve_workspace_gib * (1 << 30)), dev)
         print(f"bench: serve p50 {line['serve']['latency_ms_p50']:.1f} ms p99 "

@@ -73,8 +73,14 @@ typedef enum { SSR_F32 = 0, SSR_F16 = 1, SSR_BF16 = 2 } ssr_dtype;
  * wholly in front of or wholly behind, descend, or test a pixel: one each). */
 enum { SSR_MARCH_LINEAR = 0, SSR_MARCH_HIZ = 1 };
 
-/* Flags: drop the direct diffuse term, or the Monte-Carlo specular term. */
-enum { SSR_NO_DIRECT = 1u, SSR_NO_SPECULAR = 2u };
+/* Flags: drop the direct diffuse term, or the Monte-Carlo specular term;
+ * SSR_SAMPLER_NDF draws half vectors from the distribution of normals,
+ * density D(h) (n.h) (Walter et al. 2007, the GGX sampling Sec. 3.3 cites),
+ * instead of the visible normals: the same expectation, weights
+ * F G1(n.wo) G1(n.l) (wo.h) / ((n.wo) (n.h)), which are not bounded by one
+ * (u1 picks the azimuth, u2 the polar angle, tan^2 theta_h =
+ * rho^2 u2 / (1 - u2)). */
+enum { SSR_NO_DIRECT = 1u, SSR_NO_SPECULAR = 2u, SSR_SAMPLER_NDF = 4u };
 
 /* Per-sample hit codes written to out_hits (>= 0: hit pixel index j*W + i). */
 enum {
@@ -127,7 +133,7 @@ typedef struct {
     float thickness;   /* depth slab behind a surface that counts as a hit (>= 0) */
     uint64_t seed;     /* Philox key: (seed mod 2^32, seed >> 32)                 */
     uint32_t frame;    /* third Philox counter word                               */
-    uint32_t flags;    /* SSR_NO_DIRECT | SSR_NO_SPECULAR                         */
+    uint32_t flags;    /* SSR_NO_DIRECT | SSR_NO_SPECULAR | SSR_SAMPLER_NDF       */
 } ssr_params;
 
 /* Create a context on HIP device `device` (must be gfx950).  The context owns
@@ -193,8 +199,9 @@ int ssr_resolve(ssr_ctx* ctx, const ssr_camera* cam, const ssr_gbuffer* gbuf,
  * level and the bilinear weights of every environment lookup; a bilinear
  * lookup is differentiated inside its texel cell, so the derivative is
  * discontinuous across texel boundaries, as the function's is.  Codes
- * outside [SSR_HIT_SKIPPED, W H) count as SSR_HIT_INVALID.  Other arguments
- * and errors as ssr_shade. */
+ * outside [SSR_HIT_SKIPPED, W H) count as SSR_HIT_INVALID.  The adjoint
+ * covers the visible-normal sampler (SSR_SAMPLER_NDF: SSR_E_ARG).  Other
+ * arguments and errors as ssr_shade. */
 int ssr_shade_backward(ssr_ctx* ctx, const ssr_camera* cam, const ssr_gbuffer* gbuf,
                        const ssr_env* env, const ssr_params* params, const int32_t* hits,
                        const float* grad_rgb, float* g_normal_rough, float* g_albedo_metal,

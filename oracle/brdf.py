@@ -68,6 +68,40 @@ def sample_vndf(wo_local, alpha, u1, u2):
                               axis=-1))
 
 
+def sample_ndf(alpha, u1, u2):
+    """Half vector (local frame, z = normal) from the distribution of normals
+    itself, density D(h) (n.h) (Walter et al. 2007, the GGX sampling the paper
+    cites): azimuth 2 pi u1 and tan^2 theta_h = alpha^2 u2 / (1 - u2), i.e.
+    cos^2 theta_h = (1 - u2) / (1 + (alpha^2 - 1) u2)."""
+    alpha = np.asarray(alpha, np.float64)
+    phi = 2.0 * math.pi * u1
+    cos2 = (1.0 - u2) / (1.0 + (alpha * alpha - 1.0) * u2)
+    cos_t = np.sqrt(cos2)
+    sin_t = np.sqrt(np.clip(1.0 - cos2, 0.0, 1.0))
+    return np.stack([sin_t * np.cos(phi), sin_t * np.sin(phi), cos_t], axis=-1)
+
+
+def ndf_pdf_l(cos_oh, cos_h, alpha):
+    """Density of wi = reflect(wo, h) when h follows D(h) (n.h)."""
+    return ndf(cos_h, alpha) * cos_h / (4.0 * cos_oh)
+
+
+def weight_ndf_short(f0, cos_no, cos_nl, cos_oh, cos_h, alpha):
+    """f_s (n.wi) / p(wi) under NDF sampling, reduced:
+    F(wo.h) G1(n.wo) G1(n.wi) (wo.h) / ((n.wo) (n.h)).  Unbounded above."""
+    g = smith_g1(cos_no, alpha) * smith_g1(cos_nl, alpha) * cos_oh / (cos_no * cos_h)
+    return schlick(f0, cos_oh) * g[..., None]
+
+
+def weight_ndf_long(f0, cos_no, cos_nl, cos_oh, cos_h, alpha):
+    """The same with every factor evaluated separately (alpha > 0)."""
+    d = ndf(cos_h, alpha)
+    g = smith_g1(cos_nl, alpha) * smith_g1(cos_no, alpha)
+    f = schlick(f0, cos_oh)
+    fs = d[..., None] * f * g[..., None] / (4.0 * cos_nl * cos_no)[..., None]
+    return fs * (cos_nl / ndf_pdf_l(cos_oh, cos_h, alpha))[..., None]
+
+
 def ndf(cos_h, alpha):
     a2 = alpha * alpha
     return a2 / (math.pi * (cos_h * cos_h * (a2 - 1.0) + 1.0) ** 2)

@@ -35,6 +35,7 @@ from . import brdf, camera, env, march, philox
 
 NO_DIRECT = 1
 NO_SPECULAR = 2
+SAMPLER_NDF = 4     # draw h from D(h) (n.h) (Walter et al. 2007) instead of visible normals
 
 HIT_INVALID = -2
 HIT_BACKGROUND = -3
@@ -138,12 +139,18 @@ def shade_pixels(cam, gbuf, env_rgb, params, pix, pyramid=None, mips=None,
     a_r = rho[rep]
     t, b = brdf.onb(n_r)
     wo_local = np.stack([brdf.dot(wo_r, t), brdf.dot(wo_r, b), cos_no[rep]], axis=-1)
-    hl = brdf.sample_vndf(wo_local, a_r, u1, u2)
+    ndf_sampling = bool(flags & SAMPLER_NDF)
+    if ndf_sampling:
+        hl = brdf.sample_ndf(a_r, u1, u2)
+    else:
+        hl = brdf.sample_vndf(wo_local, a_r, u1, u2)
     h = hl[:, 0:1] * t + hl[:, 1:2] * b + hl[:, 2:3] * n_r
     cos_oh = brdf.dot(wo_r, h)
     l = 2.0 * cos_oh[:, None] * h - wo_r
     cos_nl = brdf.dot(n_r, l)
     ok = cos_nl > 0
+    if ndf_sampling:
+        ok &= cos_oh > 0          # a half vector facing away from wo reflects nothing
 
     code = np.full(rep.shape[0], HIT_INVALID, np.int64)
     nit = np.zeros(rep.shape[0], np.int64)
@@ -175,12 +182,16 @@ def shade_pixels(cam, gbuf, env_rgb, params, pix, pyramid=None, mips=None,
     L[miss] = env.bilinear(mips[0], l[miss])
 
     w = np.zeros((rep.shape[0], 3))
-    w[ok] = brdf.weight_short(f0[rep[ok]], cos_oh[ok], cos_nl[ok], a_r[ok])
+    if ndf_sampling:
+        w[ok] = brdf.weight_ndf_short(f0[rep[ok]], cos_no[rep[ok]], cos_nl[ok], cos_oh[ok],
+                                      hl[ok, 2], a_r[ok])
+    else:
+        w[ok] = brdf.weight_short(f0[rep[ok]], cos_oh[ok], cos_nl[ok], a_r[ok])
     if check_long_form:
         lf = ok & (a_r > 1e-3)
         if lf.any():
-            wl = brdf.weight_long(f0[rep[lf]], cos_no[rep[lf]], cos_nl[lf], cos_oh[lf],
-                                  hl[lf, 2], a_r[lf])
+            long_form = brdf.weight_ndf_long if ndf_sampling else brdf.weight_long
+            wl = long_form(f0[rep[lf]], cos_no[rep[lf]], cos_nl[lf], cos_oh[lf], hl[lf, 2], a_r[lf])
             assert np.allclose(wl, w[lf], rtol=1e-9, atol=1e-12), "weight forms disagree"
     contrib = (w * L).reshape(kf.size, S, 3)
     out[pf] += contrib.sum(axis=1) / S
@@ -191,12 +202,17 @@ def shade_pixels(cam, gbuf, env_rgb, params, pix, pyramid=None, mips=None,
         # each valid sample's contribution as a function of its direction,
         # with its hit pixel (or miss) held fixed
         f0o, woo, no, ao = f0[rep[ok]], wo_r[ok], n_r[ok], a_r[ok]
+        cno = cos_no[rep[ok]]
         hit_o, code_o = hit[ok], code[ok]
 
         def contribution(d):
             hh = brdf.normalize(woo + d)
             cnl = brdf.dot(no, d)
-            ww = brdf.weight_short(f0o, brdf.dot(woo, hh), np.maximum(cnl, 0.0), ao)
+            if ndf_sampling:
+                ww = brdf.weight_ndf_short(f0o, cno, np.maximum(cnl, 0.0), brdf.dot(woo, hh),
+                                           brdf.dot(no, hh), ao)
+            else:
+                ww = brdf.weight_short(f0o, brdf.dot(woo, hh), np.maximum(cnl, 0.0), ao)
             ww[cnl <= 0] = 0.0
             LL = np.empty_like(ww)
             LL[hit_o] = rad[code_o[hit_o], :3]

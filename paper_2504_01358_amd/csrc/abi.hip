@@ -74,7 +74,8 @@ int check_params(const ssr_params* p) {
     if (!(p->thickness >= 0.0f) || !finite_f(p->thickness)) return SSR_E_ARG;
     if (p->march == SSR_MARCH_LINEAR && (!(p->step_len > 0.0f) || !finite_f(p->step_len)))
         return SSR_E_ARG;
-    if (p->flags & ~static_cast<uint32_t>(SSR_NO_DIRECT | SSR_NO_SPECULAR)) return SSR_E_ARG;
+    if (p->flags & ~static_cast<uint32_t>(SSR_NO_DIRECT | SSR_NO_SPECULAR | SSR_SAMPLER_NDF))
+        return SSR_E_ARG;
     return SSR_OK;
 }
 
@@ -327,14 +328,19 @@ int ssr_shade_backward(ssr_ctx* ctx, const ssr_camera* cam, const ssr_gbuffer* g
     ssr::HizLayout hiz_lay;
     int st = prepare(ctx, cam, g, env, p, true, &a, &env_lay, &hiz_lay);
     if (st != SSR_OK) return st == 1 ? SSR_OK : st;
-    if (!hits || !grad_rgb) return SSR_E_ARG;
+    if (!hits || !grad_rgb || (p->flags & SSR_SAMPLER_NDF)) return SSR_E_ARG;
     hipStream_t s = static_cast<hipStream_t>(stream);
     st = env_mips(ctx, env, env_lay, s, &a.env);
     if (st != SSR_OK) return st;
-    st = ensure(&ctx->g_mips, &ctx->g_mips_cap, env_lay.total);
+    // copies of the environment sums that the workgroups' atomics spread
+    // over: up to 32, within 256 MB
+    const int64_t per = env_lay.total;
+    int replicas = static_cast<int>((int64_t(256) << 20) / (per * 16));
+    replicas = replicas < 1 ? 1 : (replicas > 32 ? 32 : replicas);
+    st = ensure(&ctx->g_mips, &ctx->g_mips_cap, per * replicas);
     if (st != SSR_OK) return st;
-    ssr::BackwardBuffers b{hits, grad_rgb, g_normal_rough, g_albedo_metal, g_env, g_radiance,
-                           ctx->g_mips};
+    ssr::BackwardBuffers b{hits,      grad_rgb,   g_normal_rough, g_albedo_metal,
+                           g_env,     g_radiance, ctx->g_mips,    replicas};
     return hip_status(ssr::launch_backward(a, b, g->dtype, s));
 }
 

@@ -179,21 +179,32 @@ __device__ __forceinline__ DualRGB env_bilinear_dual(const EnvLevel& lv, const D
 
 // ------------------------------------------------------------- the adjoint --
 
-constexpr int kPrivTexels = 1536;   // top mip levels summed in LDS per workgroup
+#ifndef SSR_BW_PRIV_TEXELS
+#define SSR_BW_PRIV_TEXELS 6144
+#endif
+// top mip levels summed in LDS per workgroup (72 KB: two workgroups per CU,
+// which the register use allows anyway)
+constexpr int kPrivTexels = SSR_BW_PRIV_TEXELS;
 
 struct BackArgs {
     const float* g_out;       // [H][W][3]
     const int32_t* hits;      // [H][W][spp]
     float* g_nr;              // [H][W][4] or null
     float* g_am;              // [H][W][4] or null
-    float4* g_mips;           // [env texels of all levels] (RGB), zeroed first
+    float4* g_mips;           // this workgroup's copy: [env texels of all levels] (RGB)
     float* g_rad;             // [H][W][4] or null (channels 0..2 accumulated)
     int priv_first;           // first mip level summed in LDS
     int priv_offset;          // its texel offset in the level layout
     int priv_texels;          // texels of that level and all above
+    int replicas;             // copies of the per-texel sums
+    int64_t texels;           // texels of one copy
 };
 
-__device__ __forceinline__ void add_env(float* lds, const BackArgs& b, int level_offset, int level,
+// The workgroup's sums of the top mip levels (file scope, so that the
+// compiler sees LDS and issues LDS atomics).
+__shared__ float lds_env[3 * kPrivTexels];
+
+__device__ __forceinline__ void add_env(const BackArgs& b, int level_offset, int level,
                                         const EnvTaps& t, const float coef[3]) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -201,10 +212,10 @@ __device__ __forceinline__ void add_env(float* lds, const BackArgs& b, int level
         if (w == 0.0f) continue;
         const int texel = level_offset + t.idx[k];
         if (level >= b.priv_first) {
-            float* p = lds + 3 * (texel - b.priv_offset);
-            atomicAdd(p + 0, w * coef[0]);
-            atomicAdd(p + 1, w * coef[1]);
-            atomicAdd(p + 2, w * coef[2]);
+            const int at = 3 * (texel - b.priv_offset);
+            atomicAdd(&lds_env[at + 0], w * coef[0]);
+            atomicAdd(&lds_env[at + 1], w * coef[1]);
+            atomicAdd(&lds_env[at + 2], w * coef[2]);
         } else {
             float* p = reinterpret_cast<float*>(b.g_mips + texel);
             atomicAdd(p + 0, w * coef[0]);
@@ -215,9 +226,13 @@ __device__ __forceinline__ void add_env(float* lds, const BackArgs& b, int level
 }
 
 template <int DT>
-__global__ __launch_bounds__(256) void backward_kernel(const ShadeArgs a, const BackArgs b) {
-    __shared__ float lds[3 * kPrivTexels];
-    for (int k = threadIdx.x; k < 3 * b.priv_texels; k += blockDim.x) lds[k] = 0.0f;
+__global__ __launch_bounds__(256) void backward_kernel(const ShadeArgs a, const BackArgs b0) {
+    for (int k = threadIdx.x; k < 3 * b0.priv_texels; k += blockDim.x) lds_env[k] = 0.0f;
+    // workgroups spread their global atomics over `replicas` copies of the
+    // per-texel sums, so that many pixels reading the same texels do not
+    // all queue on one address
+    BackArgs b = b0;
+    b.g_mips = b0.g_mips + static_cast<int64_t>(blockIdx.x % b0.replicas) * b0.texels;
     __syncthreads();
 
     const int tiles_x = (a.W + 15) / 16;
@@ -238,7 +253,7 @@ __global__ __launch_bounds__(256) void backward_kernel(const ShadeArgs a, const 
             EnvTaps t;
             const DV3 dd{dconst(d.x), dconst(d.y), dconst(d.z)};
             (void)env_bilinear_dual(env_level(a, 0), dd, t);
-            add_env(lds, b, 0, 0, t, g);
+            add_env(b, 0, 0, t, g);
         } else {
             const float4 nr = Texel4<DT>::load(a.normal_rough, q);
             const float4 am = Texel4<DT>::load(a.albedo_metal, q);
@@ -288,8 +303,8 @@ __global__ __launch_bounds__(256) void backward_kernel(const ShadeArgs a, const 
                     coef0[c] = kf * (1.0f - t.v);
                     coef1[c] = kf * t.v;
                 }
-                add_env(lds, b, a.env_lay.offset[k0], k0, t0, coef0);
-                if (two) add_env(lds, b, a.env_lay.offset[k1], k1, t1, coef1);
+                add_env(b, a.env_lay.offset[k0], k0, t0, coef0);
+                if (two) add_env(b, a.env_lay.offset[k1], k1, t1, coef1);
             }
 
             const int32_t* codes = b.hits + q * S;
@@ -373,7 +388,7 @@ __global__ __launch_bounds__(256) void backward_kernel(const ShadeArgs a, const 
                             atomicAdd(b.g_rad + 4 * static_cast<int64_t>(code) + 2, coef[2]);
                         }
                     } else {
-                        add_env(lds, b, 0, 0, te, coef);
+                        add_env(b, 0, 0, te, coef);
                     }
                 }
             }
@@ -390,7 +405,7 @@ __global__ __launch_bounds__(256) void backward_kernel(const ShadeArgs a, const 
     // this workgroup's sums of the top levels, one atomic per texel
     __syncthreads();
     for (int k = threadIdx.x; k < b.priv_texels; k += blockDim.x) {
-        const float* p = lds + 3 * k;
+        const float* p = lds_env + 3 * k;
         if (p[0] != 0.0f || p[1] != 0.0f || p[2] != 0.0f) {
             float* dst = reinterpret_cast<float*>(b.g_mips + b.priv_offset + k);
             atomicAdd(dst + 0, p[0]);
@@ -403,6 +418,20 @@ __global__ __launch_bounds__(256) void backward_kernel(const ShadeArgs a, const 
 __global__ void zero_kernel(float4* p, int64_t n) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i < n) p[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+}
+
+// Copy 0 += copies 1..R-1.
+__global__ void sum_replicas_kernel(float4* g, int64_t texels, int replicas) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= texels) return;
+    float4 acc = g[i];
+    for (int r = 1; r < replicas; ++r) {
+        const float4 v = g[r * texels + i];
+        acc.x += v.x;
+        acc.y += v.y;
+        acc.z += v.z;
+    }
+    g[i] = acc;
 }
 
 // g_env[y][x] += sum over levels k of g_level_k[y >> k][x >> k] / 4^k: level k
@@ -449,8 +478,11 @@ hipError_t launch_backward(const ShadeArgs& args, const BackwardBuffers& bufs, i
     b.priv_first = first;
     b.priv_offset = first < el.levels ? static_cast<int>(el.offset[first]) : 0;
     b.priv_texels = static_cast<int>(tex);
-    hipLaunchKernelGGL(zero_kernel, dim3(static_cast<unsigned>((el.total + 255) / 256)), dim3(256), 0,
-                       stream, bufs.g_mips, el.total);
+    b.replicas = bufs.replicas;
+    b.texels = el.total;
+    const int64_t all = el.total * bufs.replicas;
+    hipLaunchKernelGGL(zero_kernel, dim3(static_cast<unsigned>((all + 255) / 256)), dim3(256), 0,
+                       stream, bufs.g_mips, all);
     const dim3 grid(((args.W + 15) / 16) * ((args.H + 15) / 16));
     if (dtype == SSR_F32)
         hipLaunchKernelGGL((backward_kernel<0>), grid, dim3(256), 0, stream, args, b);
@@ -459,6 +491,9 @@ hipError_t launch_backward(const ShadeArgs& args, const BackwardBuffers& bufs, i
     else
         hipLaunchKernelGGL((backward_kernel<2>), grid, dim3(256), 0, stream, args, b);
     if (bufs.g_env) {
+        if (bufs.replicas > 1)
+            hipLaunchKernelGGL(sum_replicas_kernel, dim3(static_cast<unsigned>((el.total + 255) / 256)),
+                               dim3(256), 0, stream, bufs.g_mips, el.total, bufs.replicas);
         const int n0 = el.w[0] * el.h[0];
         hipLaunchKernelGGL(env_pushdown_kernel, dim3((n0 + 255) / 256), dim3(256), 0, stream,
                            bufs.g_mips, el, bufs.g_env);

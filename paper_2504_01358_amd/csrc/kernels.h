@@ -81,7 +81,8 @@ struct BackwardBuffers {
     float* g_albedo_metal;
     float* g_env;
     float* g_radiance;
-    float4* g_mips;           // workspace: one texel per env mip texel
+    float4* g_mips;           // workspace: `replicas` copies of one texel per env mip texel
+    int replicas;
 };
 hipError_t launch_backward(const ShadeArgs& args, const BackwardBuffers& bufs, int dtype,
                            hipStream_t stream);

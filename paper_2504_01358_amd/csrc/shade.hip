@@ -221,7 +221,7 @@ __global__ __launch_bounds__(256) void trace_linear_kernel(const ShadeArgs a) {
         int code = fill, iters = 0;
         if (P.trace) {
             const SampleDir d = sample_dir(a, P, q, s);
-            if (d.cos_nl > 0.0f) {
+            if (d.valid) {
                 const MarchResult r = march_linear(a, i, j, v3(P.X0, P.Y0, P.D), world_to_view(a, d.l));
                 code = r.code;
                 iters = r.iters;
@@ -326,7 +326,7 @@ void trace_hiz_kernel(const ShadeArgs a) {
                 HizSegment sg;
                 if (trace) {
                     const SampleDir d = sample_dir(a, P, q, k);
-                    if (d.cos_nl > 0.0f) {
+                    if (d.valid) {
                         sg = hiz_segment(a, i, j, v3(P.X0, P.Y0, P.D), world_to_view(a, d.l));
                         queue = sg.valid;
                         code = SSR_HIT_OFFSCREEN;

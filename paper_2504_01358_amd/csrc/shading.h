@@ -128,28 +128,42 @@ __device__ __forceinline__ float3 direct_term(const ShadeArgs& a, const Pixel& P
 
 struct SampleDir {
     V3 l;         // reflected ray direction (world)
-    float cos_oh, cos_nl;
+    float cos_oh, cos_nl, cos_nh;
+    bool valid;   // the sample reflects into the upper hemisphere
 };
 
 // Sample s of pixel q: Philox4x32-10 at counter (q, s, frame, 0) gives u1
-// (azimuth) and u2 (cap height) of a visible-normal sample h; l reflects wo
-// about h.
+// (azimuth) and u2 (cap height, or polar angle) of the half vector h; l
+// reflects wo about h.
 __device__ __forceinline__ SampleDir sample_dir(const ShadeArgs& a, const Pixel& P, int64_t q,
                                                 int s) {
     const uint4 x = philox4x32_10(
         make_uint4(static_cast<uint32_t>(q), static_cast<uint32_t>(s), a.frame, 0u), a.key0, a.key1);
     const float u1 = unit24(x.x), u2 = unit24(x.y);
-    // point on the spherical cap z > -ws.z: azimuth 2 pi u1, height from u2.
-    // h_std.z = z + ws.z = (1 - u2)(1 + ws.z) and 1 - z^2 = (1 - z)(1 + z) with
-    // 1 - z = u2 (1 + ws.z), 1 + z = (1 - u2)(1 + ws.z) + (1 - ws.z): no cancellation.
     float sphi, cphi;
     sincospif(2.0f * u1, &sphi, &cphi);
-    const float one_m_u2 = 1.0f - u2;
-    const float opz = 1.0f + P.ws.z;
-    const float hz = one_m_u2 * opz;
-    const float sin2 = (u2 * opz) * (hz + (1.0f - P.ws.z));
-    const float st = sqrtf(fmaxf(sin2, 0.0f));
-    const V3 hl = normalize(v3(P.rho * (st * cphi + P.ws.x), P.rho * (st * sphi + P.ws.y), hz));
+    V3 hl;
+    const bool ndf = a.flags & SSR_SAMPLER_NDF;
+    if (ndf) {
+        // distribution of normals: cos^2 theta = (1 - u2) / den and
+        // sin^2 theta = rho^2 u2 / den, den = 1 + (rho^2 - 1) u2 (no cancellation)
+        const float a2 = P.rho * P.rho;
+        const float inv = 1.0f / (1.0f + (a2 - 1.0f) * u2);
+        const float ct = sqrtf((1.0f - u2) * inv);
+        const float st = P.rho * sqrtf(u2 * inv);
+        hl = v3(st * cphi, st * sphi, ct);
+    } else {
+        // visible normals: point on the spherical cap z > -ws.z, azimuth
+        // 2 pi u1, height from u2.  h_std.z = z + ws.z = (1 - u2)(1 + ws.z)
+        // and 1 - z^2 = (1 - z)(1 + z) with 1 - z = u2 (1 + ws.z),
+        // 1 + z = (1 - u2)(1 + ws.z) + (1 - ws.z): no cancellation.
+        const float one_m_u2 = 1.0f - u2;
+        const float opz = 1.0f + P.ws.z;
+        const float hz = one_m_u2 * opz;
+        const float sin2 = (u2 * opz) * (hz + (1.0f - P.ws.z));
+        const float st = sqrtf(fmaxf(sin2, 0.0f));
+        hl = normalize(v3(P.rho * (st * cphi + P.ws.x), P.rho * (st * sphi + P.ws.y), hz));
+    }
     const V3 h = v3(hl.x * P.t.x + hl.y * P.b.x + hl.z * P.n.x,
                     hl.x * P.t.y + hl.y * P.b.y + hl.z * P.n.y,
                     hl.x * P.t.z + hl.y * P.b.z + hl.z * P.n.z);
@@ -157,10 +171,14 @@ __device__ __forceinline__ SampleDir sample_dir(const ShadeArgs& a, const Pixel&
     d.cos_oh = dot(P.wo, h);
     d.l = (2.0f * d.cos_oh) * h - P.wo;
     d.cos_nl = dot(P.n, d.l);
+    d.cos_nh = hl.z;
+    // (a visible normal always faces wo; a half vector from D may not)
+    d.valid = d.cos_nl > 0.0f && (!ndf || d.cos_oh > 0.0f);
     return d;
 }
 
-// Weight F(wo.h) G1(n.l) times the radiance found (c1 at a hit pixel, the
+// Weight F(wo.h) G1(n.l) (visible normals; NDF sampling: the weight above)
+// times the radiance found (c1 at a hit pixel, the
 // unfiltered environment otherwise), Kahan-accumulated per channel.
 template <int DT>
 __device__ __forceinline__ void accumulate(const ShadeArgs& a, const Pixel& P, const SampleDir& d,
@@ -175,7 +193,12 @@ __device__ __forceinline__ void accumulate(const ShadeArgs& a, const Pixel& P, c
     const float fc = 1.0f - d.cos_oh;
     const float fc2 = fc * fc;
     const float fr = fc2 * fc2 * fc;
-    const float g1 = smith_g1(fmaxf(d.cos_nl, 0.0f), P.rho * P.rho);
+    float g1 = smith_g1(fmaxf(d.cos_nl, 0.0f), P.rho * P.rho);
+    if (a.flags & SSR_SAMPLER_NDF) {
+        // F G1(n.wo) G1(n.l) (wo.h) / ((n.wo) (n.h)); nothing below the surface
+        g1 = d.valid ? g1 * smith_g1(P.cos_no, P.rho * P.rho) * d.cos_oh / (P.cos_no * d.cos_nh)
+                     : 0.0f;
+    }
     kahan_add(sum[0], cmp[0], (P.f0.x + (1.0f - P.f0.x) * fr) * g1 * Lr.x);
     kahan_add(sum[1], cmp[1], (P.f0.y + (1.0f - P.f0.y) * fr) * g1 * Lr.y);
     kahan_add(sum[2], cmp[2], (P.f0.z + (1.0f - P.f0.z) * fr) * g1 * Lr.z);

@@ -354,6 +354,49 @@ def test_resolve_treats_foreign_codes_as_invalid(ctx):
     assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("march", ["linear", "hiz"])
+def test_ndf_sampler_parity(ctx, march):
+    """The sampler the paper cites (Walter et al. 2007, SSR_SAMPLER_NDF):
+    parity with the oracle on the ragged multi-tile frame."""
+    kw = dict(width=203, height=117, spp=4, march=march)
+    if march == "linear":
+        kw.update(max_steps=32, max_dist=4.0)
+    sc = scenes.make_scene("c2", **kw)
+    sc.params["flags"] = 4
+    gpu, seen = run_gpu(ctx, sc.camera, gbuf_of(sc), sc.env, sc.params)
+    ref = oracle_frame(sc.camera, seen, sc.env, sc.params)
+    _check(_cmp(gpu, ref, f"ndf-{march}"), gpu, ref)
+
+
+def test_ndf_and_vndf_same_mean_different_spread(ctx):
+    """Both samplers estimate the same integral: over 16 frames their mean
+    images agree within the noise, and the NDF estimator has the larger
+    per-pixel variance (its weights are not bounded by one)."""
+    from paper_2504_01358_amd import ssr
+    sc = scenes.make_scene("c2", width=96, height=64, spp=8)
+    dev = torch.device("cuda", 0)
+    t = {k: torch.from_numpy(getattr(sc, k)).to(dev)
+         for k in ("depth", "normal_rough", "albedo_metal", "radiance", "env")}
+    args = (sc.camera, t["depth"], t["normal_rough"], t["albedo_metal"], t["radiance"], t["env"])
+    stats = {}
+    for name, fl in (("vndf", 0), ("ndf", 4)):
+        frames = [ctx.shade(*args, dict(sc.params, flags=fl | 1, frame=f)).cpu().numpy().astype(np.float64)
+                  for f in range(16)]
+        a = np.stack(frames)
+        stats[name] = (a.mean(0), a.var(0, ddof=1))
+    (mv, vv), (mn, vn) = stats["vndf"], stats["ndf"]
+    fg = np.isfinite(sc.depth)
+    se = np.sqrt((vv + vn) / 16)[fg]
+    z = np.abs(mv - mn)[fg] / np.maximum(se, 1e-12)
+    print(f"[ndf vs vndf] mean |z| {z.mean():.3f}, var ratio {vn[fg].mean() / vv[fg].mean():.3f}", flush=True)
+    assert np.median(z) < 1.5
+    assert vn[fg].mean() > vv[fg].mean()
+    with pytest.raises(ssr.SSRError):
+        hits = torch.zeros((64, 96, 8), dtype=torch.int32, device=dev)
+        ctx.shade_backward(*args, dict(sc.params, flags=4), hits,
+                           torch.zeros((64, 96, 3), device=dev))
+
+
 def test_argument_errors(ctx):
     from paper_2504_01358_amd import ssr
     sc = scenes.make_scene("c1", width=16, height=8)
@@ -362,7 +405,7 @@ def test_argument_errors(ctx):
          for k in ("depth", "normal_rough", "albedo_metal", "radiance", "env")}
     args = (sc.camera, t["depth"], t["normal_rough"], t["albedo_metal"], t["radiance"], t["env"])
     for bad in (dict(spp=0), dict(march=7), dict(max_steps=0), dict(step_len=0.0),
-                dict(max_dist=-1.0), dict(thickness=float("nan")), dict(flags=8)):
+                dict(max_dist=-1.0), dict(thickness=float("nan")), dict(flags=8), dict(flags=16)):
         with pytest.raises(ssr.SSRError):
             ctx.shade(*args, dict(sc.params, **bad))
     with pytest.raises(ssr.SSRError):

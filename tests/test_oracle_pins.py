@@ -545,3 +545,57 @@ def test_radiance_gradients_match_a_direct_difference():
             vals.append((o * g_out.reshape(-1, 3)).sum())
         assert abs((vals[0] - vals[1]) / 2e-3 - d.reshape(-1, 3)[q, c]) < 1e-8
     assert np.abs(d).sum() > 0
+
+
+# ------------------------------------------------ NDF sampling (Walter 2007) --
+
+@pytest.mark.parametrize("alpha,cos_no,f0", [(0.3, 0.8, 0.04), (0.6, 0.5, 0.9), (0.9, 0.95, 0.5),
+                                             (0.15, 0.3, 0.2)])
+def test_ndf_mean_weight_matches_quadrature(alpha, cos_no, f0):
+    """Unbiased like the visible-normal sampler: the mean NDF-sampled weight
+    converges to the same integral of f_s cos (within 4 standard errors)."""
+    rng = np.random.default_rng(int(alpha * 100 + cos_no * 10))
+    n = 400_000
+    u1, u2 = rng.uniform(size=n), rng.uniform(size=n)
+    h = brdf.sample_ndf(np.full(n, alpha), u1, u2)
+    wo = np.array([math.sqrt(1 - cos_no ** 2), 0.0, cos_no])
+    cos_oh = h @ wo
+    l = 2 * cos_oh[:, None] * h - wo
+    ok = (l[:, 2] > 0) & (cos_oh > 0)
+    w = np.zeros(n)
+    w[ok] = brdf.weight_ndf_short(np.array([f0]), np.full(ok.sum(), cos_no), l[ok, 2], cos_oh[ok],
+                                  h[ok, 2], np.full(ok.sum(), alpha))[:, 0]
+    quad = brdf.specular_albedo_quadrature(np.array([f0]), cos_no, alpha, 800, 400)[0]
+    assert abs(w.mean() - quad) < 4 * w.std() / math.sqrt(n) + 1e-4
+
+
+def test_ndf_half_vectors_follow_d_cos():
+    """The sampled cos(theta_h) has the distribution of D(h) (n.h): compare the
+    empirical CDF with the closed-form CDF u2(cos^2) = (1 - c^2)/(1 + (a^2 - 1) c^2)."""
+    alpha = 0.4
+    rng = np.random.default_rng(1)
+    u1, u2 = rng.uniform(size=200_000), rng.uniform(size=200_000)
+    c = brdf.sample_ndf(np.full(u1.size, alpha), u1, u2)[:, 2]
+    grid = np.linspace(0.2, 0.99, 9)
+    a2 = alpha * alpha
+    # P(cos theta_h <= c) = P(u2 >= u2(c)), u2(c) solving cos^2 = (1 - u2)/(1 + (a2 - 1) u2)
+    u_c = (1 - grid ** 2) / (1 + (a2 - 1) * grid ** 2)
+    emp = np.array([(c <= g).mean() for g in grid])
+    assert np.abs(emp - (1 - u_c)).max() < 5e-3
+    # and D(h) cos over the hemisphere integrates to one (the density is normalised)
+    th = np.linspace(0, math.pi / 2, 20001)
+    integral = np.trapezoid(brdf.ndf(np.cos(th), alpha) * np.cos(th) * np.sin(th) * 2 * math.pi, th)
+    assert abs(integral - 1) < 1e-6
+
+
+def test_ndf_and_vndf_frames_agree_in_the_mean():
+    """Whole estimator: a rough pixel of an open floor under a uniform map
+    gives the same mean under both samplers (many samples)."""
+    cam, g = open_floor(w=4, h=4, rough=0.5, metal=1.0, albedo=0.8)
+    envmap = np.full((8, 16, 3), 1.0)
+    base = dict(spp=8192, march=1, max_steps=64, step_len=0.125, max_dist=100.0,
+                thickness=0.05, seed=4, frame=0, flags=0)
+    q = np.array([1 * 4 + 2])
+    rv = shade.shade_pixels(cam, g, envmap, base, q)
+    rn = shade.shade_pixels(cam, g, envmap, dict(base, flags=shade.SAMPLER_NDF), q)
+    assert abs(rv["out"][0, 0] - rn["out"][0, 0]) < 0.02 * rv["out"][0, 0]
