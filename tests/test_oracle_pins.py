@@ -599,3 +599,75 @@ def test_ndf_and_vndf_frames_agree_in_the_mean():
     rv = shade.shade_pixels(cam, g, envmap, base, q)
     rn = shade.shade_pixels(cam, g, envmap, dict(base, flags=shade.SAMPLER_NDF), q)
     assert abs(rv["out"][0, 0] - rn["out"][0, 0]) < 0.02 * rv["out"][0, 0]
+
+
+# ------------------------------------------------------ first pass (c1) --
+
+def test_depth_normals_of_planes_are_exact():
+    from oracle import first_pass
+    cam, g, is_floor = floor_wall_scene(w=48, h=40)
+    n = first_pass.depth_normals(cam, g["depth"])
+    # pixels whose four neighbours lie on the same plane
+    same = is_floor.copy()
+    inner = np.zeros_like(same)
+    inner[1:-1, 1:-1] = True
+    flo = inner & is_floor & np.roll(is_floor, 1, 0) & np.roll(is_floor, -1, 0)
+    wal = inner & ~is_floor & ~np.roll(is_floor, 1, 0) & ~np.roll(is_floor, -1, 0)
+    assert flo.sum() > 100 and wal.sum() > 100
+    assert np.abs(n[flo] - [0, 1, 0]).max() < 1e-12
+    assert np.abs(n[wal] - [0, 0, 1]).max() < 1e-12       # faces the camera (+z)
+
+
+def test_depth_normals_of_spheres_converge():
+    """On the analytic spheres the finite-difference normal approaches the
+    true one; pixels next to an edge of the object are left out."""
+    import scenes
+    from oracle import first_pass
+    sc = scenes.make_scene("c1", width=256, height=256)
+    n = first_pass.depth_normals(sc.camera, sc.depth)
+    true = sc.normal_rough[..., :3].astype(np.float64)
+    ok = np.isfinite(sc.depth)
+    for ax in (0, 1):
+        for sh in (1, -1):
+            ok &= (np.roll(true, sh, ax) * true).sum(-1) > 0.995
+            ok &= np.isfinite(np.roll(sc.depth, sh, ax))
+    ok[0, :] = ok[-1, :] = ok[:, 0] = ok[:, -1] = False
+    ang = np.arccos(np.clip((n[ok] * true[ok]).sum(-1), -1, 1))
+    assert ok.sum() > 5000
+    assert np.quantile(ang, 0.99) < 0.01
+
+
+def test_brdf_table_sums_to_the_directional_albedo():
+    """F0 A + B is the integral of f_s cos with Schlick's F (linear in F0):
+    the stratified table entries agree with the quadrature of that integral,
+    and A + B = 1 for a perfect mirror."""
+    from oracle import first_pass
+    lut = first_pass.brdf_lut(n=8, k=64)
+    # (rho >= 0.15: the quadrature itself resolves the lobe there)
+    for (j, i) in ((1, 2), (2, 0), (4, 6), (7, 1), (6, 7), (3, 3)):
+        rho, mu = (j + 0.5) / 8, (i + 0.5) / 8
+        for f0 in (0.04, 0.5, 1.0):
+            q = brdf.specular_albedo_quadrature(np.array([f0]), mu, rho, 2400, 1200)[0]
+            assert abs(f0 * lut[j, i, 0] + lut[j, i, 1] - q) < 2e-3, (j, i, f0)
+    mirror = first_pass.brdf_lut(n=1, k=4)          # rho = 0.5: still a table
+    assert mirror.shape == (1, 1, 2)
+    h = brdf.sample_vndf(np.array([[0.6, 0.0, 0.8]]), np.array([0.0]), np.array([0.3]), np.array([0.7]))
+    assert np.allclose(h, [[0, 0, 1]])              # rho = 0: h = n, G1 = 1 -> A + B = 1
+
+
+def test_split_sum_is_exact_under_a_uniform_environment():
+    """With a constant environment the split-sum product is exact: the first
+    pass's specular term equals the mean of the Monte-Carlo estimator (many
+    samples, nothing to hit) and its diffuse term is a (1 - m) L."""
+    from oracle import first_pass
+    L = 1.3
+    cam, g = open_floor(w=6, h=6, rough=0.45, metal=0.5, albedo=0.7)
+    envmap = np.full((8, 16, 3), L)
+    lut = first_pass.brdf_lut(n=32, k=64)
+    c1 = first_pass.first_pass(cam, g, envmap, lut)
+    params = dict(spp=8192, march=1, max_steps=64, step_len=0.125, max_dist=100.0,
+                  thickness=0.05, seed=5, frame=0, flags=shade.NO_DIRECT)
+    q = np.array([2 * 6 + 3])
+    mc = shade.shade_pixels(cam, g, envmap, params, q)["out"][0]
+    cd = (1 - 0.5) * 0.7 * L
+    assert abs((c1.reshape(-1, 4)[q[0], 0] - cd) - mc[0]) < 0.01 * mc[0]
