@@ -40,6 +40,7 @@ def parse():
                     help="oracle sample: every k-th row (default 8)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
     ap.add_argument("--no-backward", action="store_true", help="skip the adjoint timing")
+    ap.add_argument("--no-first-pass", action="store_true", help="skip the first-pass timing")
     ap.add_argument("--serve-workspace-gib", type=float, default=6.0,
                     help="device memory for request workspaces in the serving run")
     ap.add_argument("--copy-reference", action="store_true",
@@ -329,6 +330,53 @@ def time_backward(ctx, dev, reps=20):
     return res
 
 
+def time_first_pass(ctx, scene, dev, reps=50):
+    """The first shading pass on the benchmark frame: depth normals and c1
+    (FP32 and FP16 G-buffers), average kernel time over `reps` launches.
+    Algorithmic HBM bytes per pixel: depth normals read the depth (4 B; the
+    neighbours come from cache) and write three channels; the first pass
+    reads depth, normal_rough and albedo_metal and writes c1 (the 2 MB env
+    mip chain stays in L2)."""
+    import torch
+
+    from paper_2504_01358_amd import ssr
+    H, W = scene.height, scene.width
+    stream = torch.cuda.current_stream(dev)
+    cam = ssr.make_camera(scene.camera)
+    res = {}
+    for dt in ("f32", "f16"):
+        t = upload(scene, dt, dev)
+        esz = 4 if dt == "f32" else 2
+        nr = t["normal_rough"].clone()
+        out = torch.empty_like(t["normal_rough"])
+        ssr.depth_normals(cam, t["depth"], nr, stream=stream)          # first call: table
+        ctx.first_pass(cam, t["depth"], t["normal_rough"], t["albedo_metal"], t["env"], out=out,
+                       stream=stream)
+        for name, fn, per_px in (
+                ("depth_normals", lambda: ssr.depth_normals(cam, t["depth"], nr, stream=stream),
+                 4 + 3 * esz),
+                ("first_pass", lambda: ctx.first_pass(cam, t["depth"], t["normal_rough"],
+                                                      t["albedo_metal"], t["env"], out=out,
+                                                      stream=stream),
+                 4 + 3 * 4 * esz)):
+            for _ in range(3):
+                fn()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            for _ in range(reps):
+                fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            gbs = per_px * W * H / (ms * 1e-3) / 1e9
+            res[f"{name}_{dt}"] = {"kernel_ms": ms, "bytes_per_pixel": per_px, "hbm_gbs": gbs,
+                                   "hbm_frac": gbs / HBM_PEAK_GBS}
+        del t, nr, out
+    res["workload"] = f"{W}x{H}, the shading benchmark's frame"
+    return res
+
+
 def _serving_scene_task(task):
     """One (scene, resolution) of the serving mix, FP16 G-buffer bits."""
     k, ri = task
@@ -518,6 +566,11 @@ def main():
             line[dt] = {"value": rays / (res[dt]["ms_per_step"] * 1e-3) / 1e6,
                         "ms_per_step": res[dt]["ms_per_step"], "trace_ms": res[dt]["trace_ms"],
                         "resolve_ms": res[dt]["resolve_ms"]}
+    if not args.no_first_pass:
+        line["first_pass"] = time_first_pass(ctx, scene, dev)
+        fp = line["first_pass"]["first_pass_f32"]
+        print(f"bench: first pass {fp['kernel_ms'] * 1e3:.1f} us ({fp['hbm_frac']:.2f} of HBM peak)",
+              file=sys.stderr, flush=True)
     if not args.no_backward:
         line["backward"] = time_backward(ctx, dev)
         print(f"bench: backward {line['backward']['backward_ms']:.3f} ms at 800x800 8 spp",

@@ -242,6 +242,58 @@ int64_t ssr_hiz_floats(int32_t width, int32_t height);
 int ssr_hiz_build(const float* depth, int32_t width, int32_t height, float thickness,
                   float* pyramid, void* stream);
 
+/* ------------------------------------------------------------------------
+ * First shading pass (Sec. 3.2, "Shading"): the producer of the radiance c1
+ * that ssr_shade reads at hit pixels.
+ * ------------------------------------------------------------------------ */
+
+/* Depth normals (Sec. 3.2, the G-buffer: the shading normal taken from the depth buffer by
+ * finite differences).  Each surface pixel's world point is the camera ray
+ * through its centre at its depth; the tangents along x and y are the central
+ * differences of the points of its two neighbours on that axis where both are
+ * surface pixels inside the image, the one-sided difference where only one is;
+ * the normal is their cross product, normalised and turned to face the camera
+ * (n . (camera - point) > 0).  A pixel with no neighbour on an axis, or a zero
+ * cross product, gets the unit vector toward the camera.  Background pixels
+ * (depth +inf) get (0, 0, 0).
+ * depth: [H][W] float32 device buffer (as ssr_gbuffer.depth); normal_rough:
+ * [H][W][4] device buffer in storage type `dtype` (ssr_dtype): channels 0..2
+ * are written (rounded to nearest even for the 16-bit types), channel 3 (the
+ * roughness) is left as it is, so the G-buffer's own buffer can be passed.
+ * The camera's rotation rows must be orthonormal.  SSR_E_DTYPE for an unknown
+ * dtype; SSR_E_ARG for a bad camera or a NULL buffer of a non-empty image. */
+int ssr_depth_normals(const ssr_camera* cam, const float* depth, int32_t dtype, void* normal_rough,
+                      void* stream);
+
+/* The BRDF table of the split sum (Sec. 3.2, Eq. split-sum, and Appendix C):
+ * with Schlick's Fresnel F = F0 + (1 - F0) Fc, Fc = (1 - wo.h)^5, the BRDF
+ * integral over the hemisphere is F0 A + B with A the integral of
+ * f/F (1 - Fc) cos and B that of f/F Fc cos.  lut: [n][n][2] float32 device
+ * buffer, row r for roughness (r + 1/2)/n, column c for n.v = (c + 1/2)/n,
+ * entries (A, B).  Each entry is the mean of G1(n.l) (1 - Fc) and G1(n.l) Fc
+ * (zero where n.l <= 0) over the 64 x 64 visible-normal samples
+ * (Dupuy & Benyoub 2023) at the stratified cell centres
+ * u = ((a + 1/2)/64, (b + 1/2)/64) (a fixed rule: the table is deterministic),
+ * computed in float64 and rounded to float32.  2 <= n <= 1024 (else
+ * SSR_E_ARG). */
+int ssr_brdf_lut(int32_t n, float* lut, void* stream);
+
+/* First-pass radiance (Sec. 3.2): per surface pixel, c1 = c_d + c_s with
+ * c_d = (1 - m) a E_lambda(n) (as the direct term of ssr_shade) and
+ * c_s = E_lambda(r) (F0 A + B), r = 2 (v.n) n - v the mirror direction,
+ * F0 = lerp(0.04, a, m), and (A, B) read bilinearly (texel centres at
+ * (i + 1/2)/128, clamped) from the 128 x 128 table ssr_brdf_lut builds, at
+ * (n.v, roughness); c_s = 0 where n.v <= 0.  E_lambda is the environment
+ * mip chain read at lambda = log2(1 + roughness) lambda_max.  Background
+ * pixels get 0.  Reads gbuf depth, normal_rough and albedo_metal (gbuf
+ * radiance and hiz are not read); writes out_radiance, a [H][W][4] device
+ * buffer in gbuf->dtype: (c1.r, c1.g, c1.b, 0), rounded to nearest even for
+ * the 16-bit types, the layout ssr_gbuffer.radiance takes.  out_radiance must
+ * not overlap the buffers read.  The context builds the table on its first
+ * call (and waits for it there).  Errors as ssr_shade. */
+int ssr_first_pass(ssr_ctx* ctx, const ssr_camera* cam, const ssr_gbuffer* gbuf,
+                   const ssr_env* env, void* out_radiance, void* stream);
+
 /* Philox4x32-10 (Salmon et al., SC'11) of n counters: ctr [n][4], key [n][2],
  * out [n][4], all uint32 device buffers.  The same generator ssr_shade draws
  * its samples from. */

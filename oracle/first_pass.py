@@ -38,8 +38,8 @@ import numpy as np
 from . import brdf, camera, env
 
 
-def depth_normals(cam, depth):
-    """World-space unit normals [H][W][3] from the depth buffer."""
+def _tangents(cam, depth):
+    """World points of the pixel centres and the two tangents of each pixel."""
     c = camera.unpack(cam)
     W, H = c["W"], c["H"]
     D = np.asarray(depth, np.float64)
@@ -70,6 +70,12 @@ def depth_normals(cam, depth):
 
     dx, hx = tangent(1)
     dy, hy = tangent(0)
+    return c, P, fin, dx, hx, dy, hy
+
+
+def depth_normals(cam, depth):
+    """World-space unit normals [H][W][3] from the depth buffer."""
+    c, P, fin, dx, hx, dy, hy = _tangents(cam, depth)
     n = np.cross(dx, dy)
     to_cam = c["pos"] - P
     ok = hx & hy & (np.linalg.norm(n, axis=-1) > 0)
@@ -79,6 +85,21 @@ def depth_normals(cam, depth):
     n[flip] = -n[flip]
     n[~fin] = 0.0
     return n
+
+
+def depth_normal_condition(cam, depth):
+    """|t_x| |t_y| / |t_x x t_y| per pixel: how much a relative error in the
+    two tangents turns the normal (one over the sine of their angle).  Inf
+    where the cross product vanishes; 1 where the normal falls back to the
+    direction toward the camera.  The conditioning of the pixel, not part of
+    the method."""
+    _, _, fin, dx, hx, dy, hy = _tangents(cam, depth)
+    cr = np.linalg.norm(np.cross(dx, dy), axis=-1)
+    num = np.linalg.norm(dx, axis=-1) * np.linalg.norm(dy, axis=-1)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        k = np.where(cr > 0, num / np.where(cr > 0, cr, 1.0), np.inf)
+    k = np.where(hx & hy, k, 1.0)
+    return np.where(fin, k, 0.0)
 
 
 def brdf_lut(n=128, k=64):
@@ -122,11 +143,14 @@ def lut_lookup(lut, mu, rho):
             + (1 - fx) * fy * lut[y1, x0] + fx * fy * lut[y1, x1])
 
 
-def first_pass_bound(cam, gbuf, env_rgb, lut, eps=1e-6):
-    """How far each c1 can move when a component of the stored normal is off
-    by a relative eps (its float32 rounding), to first order: the
-    conditioning of the pixel (both lookups move with the normal)."""
-    base = first_pass(cam, gbuf, env_rgb, lut)
+def first_pass_bound(cam, gbuf, env_rgb, lut, eps=1e-6, pix=None):
+    """How far each c1 can move, to first order, when a component of the
+    stored normal is off by a relative eps (its rounding; zero components stay
+    zero) or the mirror direction is turned by eps radians (the rounding of
+    the directions derived from the normal and the view ray): the
+    conditioning of the pixel, not part of the method."""
+    mips = env.build_mips(np.asarray(env_rgb, np.float64))
+    base = first_pass(cam, gbuf, env_rgb, lut, pix=pix, mips=mips)
     worst = np.zeros_like(base)
     for k in range(3):
         for sgn in (1.0, -1.0):
@@ -134,22 +158,32 @@ def first_pass_bound(cam, gbuf, env_rgb, lut, eps=1e-6):
             nr = np.array(gbuf["normal_rough"], np.float64)
             nr[..., k] *= 1.0 + sgn * eps
             g["normal_rough"] = nr
-            worst = np.maximum(worst, np.abs(first_pass(cam, g, env_rgb, lut) - base))
+            worst = np.maximum(worst, np.abs(first_pass(cam, g, env_rgb, lut, pix=pix,
+                                                        mips=mips) - base))
+    for k in range(2):
+        for sgn in (1.0, -1.0):
+            worst = np.maximum(worst, np.abs(first_pass(cam, gbuf, env_rgb, lut, pix=pix, mips=mips,
+                                                        _turn_r=(k, sgn * eps)) - base))
     return worst
 
 
-def first_pass(cam, gbuf, env_rgb, lut):
-    """c1 [H][W][4] = (c_d + c_s, 0) per pixel (float64)."""
+def first_pass(cam, gbuf, env_rgb, lut, pix=None, mips=None, _turn_r=None):
+    """c1 [H][W][4] = (c_d + c_s, 0) per pixel (float64); with ``pix`` (flat
+    pixel indices) only those pixels, as [n][4].  (``_turn_r`` = (k, angle)
+    turns each mirror direction toward its k-th tangent, for the bound.)"""
     c = camera.unpack(cam)
     W, H = c["W"], c["H"]
     D = np.asarray(gbuf["depth"], np.float64).reshape(-1)
     nr = np.asarray(gbuf["normal_rough"], np.float64).reshape(-1, 4)
     am = np.asarray(gbuf["albedo_metal"], np.float64).reshape(-1, 4)
-    mips = env.build_mips(np.asarray(env_rgb, np.float64))
+    if mips is None:
+        mips = env.build_mips(np.asarray(env_rgb, np.float64))
+    sel = np.arange(W * H) if pix is None else np.asarray(pix, np.int64).reshape(-1)
     out = np.zeros((W * H, 4))
-    fg = np.nonzero(np.isfinite(D))[0]
+    shape = (H, W, 4) if pix is None else (sel.size, 4)
+    fg = sel[np.isfinite(D[sel])]
     if fg.size == 0:
-        return out.reshape(H, W, 4)
+        return out[sel].reshape(shape)
     i, j = fg % W, fg // W
     V0 = camera.pixel_view_point(c, i.astype(np.float64), j.astype(np.float64), D[fg])
     wo = -camera.view_to_world_dir(c, V0)
@@ -163,9 +197,12 @@ def first_pass(cam, gbuf, env_rgb, lut):
     cd = (1.0 - m)[:, None] * a * env.trilinear(mips, n, lam)
     cos_nv = brdf.dot(n, wo)
     r = 2.0 * cos_nv[:, None] * n - wo
+    if _turn_r is not None:
+        tan = brdf.onb(r)[_turn_r[0]]
+        r = math.cos(_turn_r[1]) * r + math.sin(_turn_r[1]) * tan
     ab = lut_lookup(lut, np.clip(cos_nv, 0.0, 1.0), rho)
     fs = f0 * ab[:, 0:1] + ab[:, 1:2]
     cs = env.trilinear(mips, r, lam) * fs
     cs[cos_nv <= 0] = 0.0
     out[fg, :3] = cd + cs
-    return out.reshape(H, W, 4)
+    return out[sel].reshape(shape)

@@ -13,7 +13,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libssr.so")
-SOURCES = ["abi.hip", "pyramids.hip", "shade.hip", "session.hip", "backward.hip"]
+SOURCES = ["abi.hip", "pyramids.hip", "shade.hip", "session.hip", "backward.hip", "first_pass.hip"]
 
 
 def command(out=LIB, extra=()):

@@ -22,7 +22,13 @@ struct ssr_ctx {
     int* counter;
     float4* g_mips;     // adjoint: environment derivatives per mip texel
     int64_t g_mips_cap;
+    float2* lut;        // first pass: split-sum table [kLutN][kLutN], built on first use
 };
+
+namespace {
+constexpr int kLutN = 128;   // table entries per axis (n.v and roughness)
+constexpr int kLutK = 64;    // stratified samples per axis of each entry
+}  // namespace
 
 namespace {
 
@@ -79,25 +85,8 @@ int check_params(const ssr_params* p) {
     return SSR_OK;
 }
 
-}  // namespace
-
-namespace ssr {
-
-int fill_args(const ssr_camera* cam, const ssr_gbuffer* g, const ssr_env* env, const ssr_params* p,
-              bool need_env, ShadeArgs* a, EnvLayout* env_lay, HizLayout* hiz_lay) {
-    if (!g || (need_env && !env)) return SSR_E_ARG;
-    int st = check_camera(cam);
-    if (st != SSR_OK) return st;
-    st = check_params(p);
-    if (st != SSR_OK) return st;
-    if (g->dtype != SSR_F32 && g->dtype != SSR_F16 && g->dtype != SSR_BF16) return SSR_E_DTYPE;
-    if (need_env && (!env->rgb || !make_env_layout(env->width, env->height, env_lay)))
-        return SSR_E_ARG;
-    if (cam->width == 0 || cam->height == 0) return 1;
-    if (!g->depth || !g->normal_rough || !g->albedo_metal || !g->radiance) return SSR_E_ARG;
-    // (the hierarchical march needs the pyramid; the layout also bounds W H)
-    if (!make_hiz_layout(cam->width, cam->height, hiz_lay)) return SSR_E_ARG;
-
+// Zero `a` and fill its camera fields.
+void camera_args(const ssr_camera* cam, ssr::ShadeArgs* a) {
     memset(a, 0, sizeof(*a));
     a->W = cam->width;
     a->H = cam->height;
@@ -112,12 +101,37 @@ int fill_args(const ssr_camera* cam, const ssr_gbuffer* g, const ssr_env* env, c
     a->cx = cam->cx;
     a->cy = cam->cy;
     a->z_near = cam->z_near;
+}
+
+}  // namespace
+
+namespace ssr {
+
+int fill_args(const ssr_camera* cam, const ssr_gbuffer* g, const ssr_env* env, const ssr_params* p,
+              bool need_env, ShadeArgs* a, EnvLayout* env_lay, HizLayout* hiz_lay) {
+    if (!g || (need_env && !env)) return SSR_E_ARG;
+    int st = check_camera(cam);
+    if (st != SSR_OK) return st;
+    if (p) {
+        st = check_params(p);
+        if (st != SSR_OK) return st;
+    }
+    if (g->dtype != SSR_F32 && g->dtype != SSR_F16 && g->dtype != SSR_BF16) return SSR_E_DTYPE;
+    if (need_env && (!env->rgb || !make_env_layout(env->width, env->height, env_lay)))
+        return SSR_E_ARG;
+    if (cam->width == 0 || cam->height == 0) return 1;
+    if (!g->depth || !g->normal_rough || !g->albedo_metal || !g->radiance) return SSR_E_ARG;
+    // (the hierarchical march needs the pyramid; the layout also bounds W H)
+    if (!make_hiz_layout(cam->width, cam->height, hiz_lay)) return SSR_E_ARG;
+
+    camera_args(cam, a);
     a->depth = g->depth;
     a->normal_rough = g->normal_rough;
     a->albedo_metal = g->albedo_metal;
     a->radiance = g->radiance;
     a->hiz_lay = *hiz_lay;
     if (need_env) a->env_lay = *env_lay;
+    if (!p) return SSR_OK;
     a->spp = p->spp;
     a->max_steps = p->max_steps;
     // linear march: samples t_k = k * step_len for k = 1..K, K = min(max_steps,
@@ -180,6 +194,7 @@ int ssr_ctx_create(int device, ssr_ctx** out) {
     c->counter = nullptr;
     c->g_mips = nullptr;
     c->g_mips_cap = 0;
+    c->lut = nullptr;
     if (hipSetDevice(device) != hipSuccess ||
         hipMalloc(reinterpret_cast<void**>(&c->counter), 256) != hipSuccess) {
         (void)hipGetLastError();
@@ -199,6 +214,7 @@ void ssr_ctx_destroy(ssr_ctx* ctx) {
         if (ctx->codes) (void)hipFree(ctx->codes);
         if (ctx->counter) (void)hipFree(ctx->counter);
         if (ctx->g_mips) (void)hipFree(ctx->g_mips);
+        if (ctx->lut) (void)hipFree(ctx->lut);
     }
     delete ctx;
 }
@@ -367,6 +383,57 @@ int ssr_shade(ssr_ctx* ctx, const ssr_camera* cam, const ssr_gbuffer* g, const s
     if (st != SSR_OK) return st;
     a.out = out_rgb;
     return hip_status(ssr::launch_resolve(a, g->dtype, s));
+}
+
+int ssr_depth_normals(const ssr_camera* cam, const float* depth, int32_t dtype, void* normal_rough,
+                      void* stream) {
+    int st = check_camera(cam);
+    if (st != SSR_OK) return st;
+    if (dtype != SSR_F32 && dtype != SSR_F16 && dtype != SSR_BF16) return SSR_E_DTYPE;
+    if (cam->width == 0 || cam->height == 0) return SSR_OK;
+    if (!depth || !normal_rough) return SSR_E_ARG;
+    ssr::ShadeArgs a;
+    camera_args(cam, &a);
+    a.depth = depth;
+    return hip_status(ssr::launch_depth_normals(a, dtype, normal_rough,
+                                                static_cast<hipStream_t>(stream)));
+}
+
+int ssr_brdf_lut(int32_t n, float* lut, void* stream) {
+    if (n < 2 || n > 1024 || !lut) return SSR_E_ARG;
+    return hip_status(ssr::launch_brdf_lut(reinterpret_cast<float2*>(lut), n, kLutK,
+                                           static_cast<hipStream_t>(stream)));
+}
+
+int ssr_first_pass(ssr_ctx* ctx, const ssr_camera* cam, const ssr_gbuffer* g, const ssr_env* env,
+                   void* out_radiance, void* stream) {
+    if (!ctx || !g) return SSR_E_ARG;
+    ssr_gbuffer gg = *g;
+    gg.radiance = out_radiance;  // the output; the input radiance is not read
+    ssr::ShadeArgs a;
+    ssr::EnvLayout env_lay;
+    ssr::HizLayout hiz_lay;
+    int st = ssr::fill_args(cam, &gg, env, nullptr, true, &a, &env_lay, &hiz_lay);
+    if (st != SSR_OK) return st == 1 ? SSR_OK : st;
+    if (hipSetDevice(ctx->device) != hipSuccess) return SSR_E_HIP;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (!ctx->lut) {
+        // built once; the wait makes it visible to calls on any stream
+        void* p = nullptr;
+        if (hipMalloc(&p, sizeof(float2) * kLutN * kLutN) != hipSuccess) {
+            (void)hipGetLastError();
+            return SSR_E_NOMEM;
+        }
+        if (ssr::launch_brdf_lut(static_cast<float2*>(p), kLutN, kLutK, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) {
+            (void)hipFree(p);
+            return SSR_E_HIP;
+        }
+        ctx->lut = static_cast<float2*>(p);
+    }
+    st = env_mips(ctx, env, env_lay, s, &a.env);
+    if (st != SSR_OK) return st;
+    return hip_status(ssr::launch_first_pass(a, g->dtype, ctx->lut, kLutN, out_radiance, s));
 }
 
 }  // extern "C"

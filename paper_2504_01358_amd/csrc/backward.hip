@@ -127,8 +127,8 @@ __device__ __forceinline__ DualRGB env_bilinear_dual(const EnvLevel& lv, const D
     const V3 d = value(dir);
     const EnvAngles a = env_angles(d);
     const float wf = static_cast<float>(lv.w), hf = static_cast<float>(lv.h);
-    const TexelCoord cx = texel_coord(a.phi, kInv2PiHi * wf, kInv2PiLo * wf, 0.5f * wf - 0.5f);
-    const TexelCoord cy = texel_coord(a.theta, kInvPiHi * hf, kInvPiLo * hf, -0.5f);
+    TexelCoord cx, cy;
+    env_texel(lv, a, cx, cy);
     int x0 = cx.i0 % lv.w;
     if (x0 < 0) x0 += lv.w;
     int x1 = x0 + 1;

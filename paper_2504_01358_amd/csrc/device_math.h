@@ -1,6 +1,6 @@
 // Device helpers shared by the shading kernels: counter-based random numbers,
 // equirect environment filtering and the GGX microfacet pieces.  Everything
-// is float32 (no float64 on the device); where a plain formula would lose
+// is float32 (the shading kernels use no float64); where a plain formula would lose
 // accuracy that the environment map's contrast turns into visible error, the
 // evaluation is rearranged (comments say how) so that it stays exact to a few
 // float32 ulps of the sampled direction.
@@ -69,6 +69,14 @@ __device__ __forceinline__ V3 normalize(V3 a) {
 // full accuracy near the poles, where acos(d.y) does not).  Texel coordinate
 // x = (W/2 - 1/2) + phi * W/(2 pi), y = theta * H/pi - 1/2.
 //
+// Near phi = +-pi (the seam, d.z > 0) and theta = pi (the lower pole) a
+// float32 angle has an absolute error of an ulp of pi, far more than the
+// direction's own.  There the angle is measured from the nearer reference
+// instead: for d.z > 0, x = -1/2 - atan2(d.x, d.z) W/(2 pi) (the same
+// position modulo W, as the map wraps), and for d.y < 0,
+// y = (H - 1/2) - atan2(|d.xz|, -d.y) H/pi.  Both have the derivatives of
+// phi and theta.
+//
 // The products are carried as float-float values: the scale constants come
 // in (hi, lo) pairs, the product error is recovered with an FMA and the sum
 // with the offset by an exact two-sum, so the fractional texel position is
@@ -106,11 +114,15 @@ __device__ __forceinline__ TexelCoord texel_coord(float ang, float scale_hi, flo
 }
 
 struct EnvAngles {
-    float phi, theta;
+    float phi, theta;  // measured from the references above
+    bool front, low;   // d.z > 0 (from the seam), d.y < 0 (from the lower pole)
 };
 
 __device__ __forceinline__ EnvAngles env_angles(V3 d) {
-    return EnvAngles{atan2f(d.x, -d.z), atan2f(sqrtf(d.x * d.x + d.z * d.z), d.y)};
+    const bool front = d.z > 0.0f, low = d.y < 0.0f;
+    const float r = sqrtf(d.x * d.x + d.z * d.z);
+    return EnvAngles{front ? -atan2f(d.x, d.z) : atan2f(d.x, -d.z),
+                     low ? -atan2f(r, -d.y) : atan2f(r, d.y), front, low};
 }
 
 // 1/(2 pi) and 1/pi as float-float pairs (hi + lo to ~1e-15).
@@ -119,11 +131,18 @@ constexpr float kInv2PiLo = 0x1.b93910p-28f;  // 6.4206382e-09
 constexpr float kInvPiHi = 0x1.45f306p-2f;    // 0.31830987
 constexpr float kInvPiLo = 0x1.b93910p-27f;   // 1.2841276e-08
 
-__device__ __forceinline__ float3 env_bilinear(const EnvLevel& lv, EnvAngles a) {
+// Texel coordinates of the angles in a w x h level.
+__device__ __forceinline__ void env_texel(const EnvLevel& lv, const EnvAngles& a, TexelCoord& cx,
+                                          TexelCoord& cy) {
     const float wf = static_cast<float>(lv.w);
     const float hf = static_cast<float>(lv.h);
-    const TexelCoord cx = texel_coord(a.phi, kInv2PiHi * wf, kInv2PiLo * wf, 0.5f * wf - 0.5f);
-    const TexelCoord cy = texel_coord(a.theta, kInvPiHi * hf, kInvPiLo * hf, -0.5f);
+    cx = texel_coord(a.phi, kInv2PiHi * wf, kInv2PiLo * wf, a.front ? -0.5f : 0.5f * wf - 0.5f);
+    cy = texel_coord(a.theta, kInvPiHi * hf, kInvPiLo * hf, a.low ? hf - 0.5f : -0.5f);
+}
+
+__device__ __forceinline__ float3 env_bilinear(const EnvLevel& lv, EnvAngles a) {
+    TexelCoord cx, cy;
+    env_texel(lv, a, cx, cy);
     int x0 = cx.i0 % lv.w;
     if (x0 < 0) x0 += lv.w;
     int x1 = x0 + 1;

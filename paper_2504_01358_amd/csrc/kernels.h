@@ -86,6 +86,13 @@ struct BackwardBuffers {
 };
 hipError_t launch_backward(const ShadeArgs& args, const BackwardBuffers& bufs, int dtype,
                            hipStream_t stream);
+// First pass: depth normals into channels 0..2 of `out` ([H][W][4] in the
+// storage type `dtype`), the split-sum table ([n][n] (A, B) pairs from k x k
+// samples each) and c1 into `out` ([H][W][4] in `dtype`).
+hipError_t launch_depth_normals(const ShadeArgs& args, int dtype, void* out, hipStream_t stream);
+hipError_t launch_brdf_lut(float2* lut, int n, int k, hipStream_t stream);
+hipError_t launch_first_pass(const ShadeArgs& args, int dtype, const float2* lut, int n, void* out,
+                             hipStream_t stream);
 hipError_t launch_philox(const uint32_t* ctr, const uint32_t* key, int64_t n, uint32_t* out,
                          hipStream_t stream);
 

@@ -96,6 +96,27 @@ __device__ __forceinline__ Pixel setup_pixel(const ShadeArgs& a, int i, int j, i
     return P;
 }
 
+// Mip level lambda = log2(1 + rho) * lambda_max of the roughness lookups
+// (Sec. 3.2), via log1p (no rounding of 1 + rho), clamped to [0, top].
+__device__ __forceinline__ float roughness_lod(const ShadeArgs& a, float rho) {
+    const int top = a.env_lay.levels - 1;
+    return fminf(fmaxf(log1pf(rho) * (static_cast<float>(top) * 1.44269504f), 0.0f),
+                 static_cast<float>(top));
+}
+
+// E_lambda(d): the two mip levels around lambda, each read bilinearly, blended.
+__device__ __forceinline__ float3 env_lod(const ShadeArgs& a, const EnvAngles& ang, float lam) {
+    const int top = a.env_lay.levels - 1;
+    const int k0 = static_cast<int>(floorf(lam));
+    const int k1 = min(k0 + 1, top);
+    const float t = lam - static_cast<float>(k0);
+    const float3 e0 = env_bilinear(env_level(a, k0), ang);
+    if (!(t > 0.0f)) return e0;
+    const float3 e1 = env_bilinear(env_level(a, k1), ang);
+    return make_float3((1.0f - t) * e0.x + t * e1.x, (1.0f - t) * e0.y + t * e1.y,
+                       (1.0f - t) * e0.z + t * e1.z);
+}
+
 // Direct diffuse c_d = (1 - m) a E_lambda(n), or the environment seen directly
 // for a background pixel.
 __device__ __forceinline__ float3 direct_term(const ShadeArgs& a, const Pixel& P, int i, int j) {
@@ -105,21 +126,7 @@ __device__ __forceinline__ float3 direct_term(const ShadeArgs& a, const Pixel& P
         return env_bilinear(env_level(a, 0), env_angles(d));
     }
     if (a.flags & SSR_NO_DIRECT) return make_float3(0.0f, 0.0f, 0.0f);
-    const int top = a.env_lay.levels - 1;
-    // lambda = log2(1 + rho) * lambda_max, via log1p (no rounding of 1 + rho)
-    const float lam = fminf(fmaxf(log1pf(P.rho) * (static_cast<float>(top) * 1.44269504f), 0.0f),
-                            static_cast<float>(top));
-    const int k0 = static_cast<int>(floorf(lam));
-    const int k1 = min(k0 + 1, top);
-    const float t = lam - static_cast<float>(k0);
-    const EnvAngles ang = env_angles(P.n);
-    const float3 e0 = env_bilinear(env_level(a, k0), ang);
-    float3 e = e0;
-    if (t > 0.0f) {
-        const float3 e1 = env_bilinear(env_level(a, k1), ang);
-        e = make_float3((1.0f - t) * e0.x + t * e1.x, (1.0f - t) * e0.y + t * e1.y,
-                        (1.0f - t) * e0.z + t * e1.z);
-    }
+    const float3 e = env_lod(a, env_angles(P.n), roughness_lod(a, P.rho));
     const float k = 1.0f - P.m;
     return make_float3(k * P.alb.x * e.x, k * P.alb.y * e.y, k * P.alb.z * e.z);
 }

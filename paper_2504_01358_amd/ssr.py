@@ -26,7 +26,7 @@ SYMBOLS = ("ssr_ctx_create", "ssr_ctx_destroy", "ssr_shade", "ssr_trace", "ssr_r
            "ssr_philox4x32_10", "ssr_status_string", "ssr_session_create",
            "ssr_session_add_scene", "ssr_session_request_bytes", "ssr_session_submit",
            "ssr_session_poll", "ssr_session_wait", "ssr_session_get_stats",
-           "ssr_session_destroy")
+           "ssr_session_destroy", "ssr_depth_normals", "ssr_brdf_lut", "ssr_first_pass")
 
 PENDING = 1
 
@@ -128,6 +128,12 @@ def _load():
     lib.ssr_session_get_stats.restype = ctypes.c_int
     lib.ssr_session_destroy.argtypes = [vp]
     lib.ssr_session_destroy.restype = None
+    lib.ssr_depth_normals.argtypes = [P(Camera), vp, ctypes.c_int32, vp, vp]
+    lib.ssr_depth_normals.restype = ctypes.c_int
+    lib.ssr_brdf_lut.argtypes = [ctypes.c_int32, vp, vp]
+    lib.ssr_brdf_lut.restype = ctypes.c_int
+    lib.ssr_first_pass.argtypes = [vp, P(Camera), P(GBuffer), P(Env), vp, vp]
+    lib.ssr_first_pass.restype = ctypes.c_int
     lib.ssr_status_string.argtypes = [ctypes.c_int]
     lib.ssr_status_string.restype = ctypes.c_char_p
     return lib
@@ -329,6 +335,53 @@ def _shade_backward(self, camera, depth, normal_rough, albedo_metal, radiance, e
 
 
 Context.shade_backward = _shade_backward
+
+
+def _first_pass(self, camera, depth, normal_rough, albedo_metal, env, env_mips=None, out=None,
+                stream=None):
+    """First-pass radiance c1 = c_d + c_s: returns ``out`` [H][W][4] in the
+    G-buffer's dtype, (c1, 0) per pixel, the layout the ``radiance`` argument
+    of ``shade`` takes."""
+    cam = camera if isinstance(camera, Camera) else make_camera(camera)
+    H, W = cam.height, cam.width
+    if out is None:
+        out = torch.empty((H, W, 4), dtype=normal_rough.dtype, device=depth.device)
+    g = Context._gbuf(cam, depth, normal_rough, albedo_metal, out, None)
+    e = Context._env(env, env_mips)
+    st = lib.ssr_first_pass(self._h, ctypes.byref(cam), ctypes.byref(g), ctypes.byref(e),
+                            _ptr(out), _stream(stream, depth.device))
+    _check(st, "ssr_first_pass")
+    return out
+
+
+Context.first_pass = _first_pass
+
+
+def depth_normals(camera, depth, normal_rough=None, dtype=torch.float32, stream=None):
+    """Depth normals into channels 0..2 of ``normal_rough`` [H][W][4] (a new
+    zeroed tensor of ``dtype`` when None; channel 3 is left as it is)."""
+    cam = camera if isinstance(camera, Camera) else make_camera(camera)
+    H, W = cam.height, cam.width
+    _dev_tensor(depth, "depth", torch.float32, (H, W))
+    if normal_rough is None:
+        normal_rough = torch.zeros((H, W, 4), dtype=dtype, device=depth.device)
+    if normal_rough.dtype not in _GBUF_DTYPES:
+        raise TypeError(f"unsupported G-buffer dtype {normal_rough.dtype}")
+    _dev_tensor(normal_rough, "normal_rough", normal_rough.dtype, (H, W, 4))
+    _check(lib.ssr_depth_normals(ctypes.byref(cam), _ptr(depth), _GBUF_DTYPES[normal_rough.dtype],
+                                 _ptr(normal_rough), _stream(stream, depth.device)),
+           "ssr_depth_normals")
+    return normal_rough
+
+
+def brdf_lut(n=128, out=None, device=None, stream=None):
+    """The split-sum BRDF table [n][n][2] float32 (rows roughness, columns n.v)."""
+    if out is None:
+        out = torch.empty((n, n, 2), dtype=torch.float32,
+                          device=device if device is not None else torch.device("cuda", 0))
+    _dev_tensor(out, "out", torch.float32, (n, n, 2))
+    _check(lib.ssr_brdf_lut(int(n), _ptr(out), _stream(stream, out.device)), "ssr_brdf_lut")
+    return out
 
 
 class Session:

@@ -36,7 +36,7 @@ def declared_functions():
 
 def test_every_declared_symbol_is_exported(lib):
     names = declared_functions()
-    assert len(names) == 20, names
+    assert len(names) == 23, names
     raw = ctypes.CDLL(LIB)
     for n in names:
         assert hasattr(raw, n), n
@@ -132,5 +132,19 @@ def test_host_side_argument_checks(lib):
     assert raw.ssr_session_wait(None, 1, None) == -1
     assert raw.ssr_session_request_bytes(None, None) == -1
     assert raw.ssr_session_get_stats(None, None) == -1
+    # first pass: null context, bad table sizes, bad camera or storage type
+    assert raw.ssr_first_pass(None, byref(cam), byref(g), byref(e), None, None) == -1
+    for n in (-1, 0, 1, 1025):
+        assert raw.ssr_brdf_lut(n, ctypes.c_void_p(16), None) == -1
+    assert raw.ssr_brdf_lut(128, None, None) == -1
+    assert raw.ssr_depth_normals(byref(cam), None, 0, None, None) == -1   # fx = 0
+    ok = lib.Camera()
+    ok.fx = ok.fy = 100.0
+    ok.z_near = 0.01
+    ok.rot[0] = ok.rot[4] = ok.rot[8] = 1.0
+    assert raw.ssr_depth_normals(byref(ok), None, 0, None, None) == 0     # empty image
+    assert raw.ssr_depth_normals(byref(ok), None, 3, None, None) == -2
+    ok.width, ok.height = 4, 4
+    assert raw.ssr_depth_normals(byref(ok), None, 0, None, None) == -1    # null buffers
     raw.ssr_session_destroy(None)
     raw.ssr_ctx_destroy(None)

@@ -671,3 +671,22 @@ def test_split_sum_is_exact_under_a_uniform_environment():
     mc = shade.shade_pixels(cam, g, envmap, params, q)["out"][0]
     cd = (1 - 0.5) * 0.7 * L
     assert abs((c1.reshape(-1, 4)[q[0], 0] - cd) - mc[0]) < 0.01 * mc[0]
+
+
+def test_depth_normal_condition_and_pixel_subset():
+    """A wall facing the camera has perpendicular tangents (condition 1); the
+    first pass on a subset of pixels equals the full frame at those pixels."""
+    from oracle import first_pass
+    cam, g, is_floor = floor_wall_scene(w=48, h=40)
+    k = first_pass.depth_normal_condition(cam, g["depth"])
+    wall = ~is_floor
+    wall[0, :] = wall[-1, :] = wall[:, 0] = wall[:, -1] = False
+    wall &= ~np.roll(is_floor, 1, 0) & ~np.roll(is_floor, -1, 0)
+    assert wall.sum() > 100 and np.abs(k[wall] - 1.0).max() < 1e-9
+    assert np.all(k[is_floor] >= 1.0)
+    lut = first_pass.brdf_lut(n=8, k=8)
+    env_rgb = np.exp(np.random.default_rng(2).normal(0, 1, (16, 32, 3)))
+    full = first_pass.first_pass(cam, g, env_rgb, lut)
+    pix = np.array([0, 5, 100, 48 * 40 - 1, 777])
+    sub = first_pass.first_pass(cam, g, env_rgb, lut, pix=pix)
+    assert np.array_equal(sub, full.reshape(-1, 4)[pix])
