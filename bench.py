@@ -192,8 +192,11 @@ def time_gpu(ctx, scene, dtype, steps, warmup, dev, mips):
     stream = torch.cuda.current_stream(dev)
     cam = ssr.make_camera(scene.camera)
     prm = ssr.make_params(scene.params)
-
-    codes = torch.empty((H, W, S), dtype=torch.int32, device=dev)
+    # the timed frames keep their codes tile-major, as ssr_shade does for its own
+    # workspace (same values, far fewer partial-line writes)
+    prm_t = ssr.make_params(dict(scene.params,
+                                 flags=int(scene.params.get("flags", 0)) | ssr.CODES_TILED))
+    codes = torch.empty(ssr.codes_shape(W, H, S, ssr.CODES_TILED), dtype=torch.int32, device=dev)
 
     def step(ev=None):
         if ev is not None:
@@ -201,12 +204,12 @@ def time_gpu(ctx, scene, dtype, steps, warmup, dev, mips):
         ssr.hiz_build(t["depth"], scene.params["thickness"], out=hiz, stream=stream)
         if ev is not None:
             ev[1].record(stream)
-        ctx.trace(cam, t["depth"], t["normal_rough"], t["albedo_metal"], t["radiance"], prm,
+        ctx.trace(cam, t["depth"], t["normal_rough"], t["albedo_metal"], t["radiance"], prm_t,
                   hiz=hiz, hits=codes, stream=stream)
         if ev is not None:
             ev[2].record(stream)
         ctx.resolve(cam, t["depth"], t["normal_rough"], t["albedo_metal"], t["radiance"], t["env"],
-                    prm, codes, env_mips=mips, out=out, stream=stream)
+                    prm_t, codes, env_mips=mips, out=out, stream=stream)
         if ev is not None:
             ev[3].record(stream)
 

@@ -82,6 +82,18 @@ enum { SSR_MARCH_LINEAR = 0, SSR_MARCH_HIZ = 1 };
  * rho^2 u2 / (1 - u2)). */
 enum { SSR_NO_DIRECT = 1u, SSR_NO_SPECULAR = 2u, SSR_SAMPLER_NDF = 4u };
 
+/* Layout flag of the per-sample buffers (hit codes and iteration counts) of
+ * ssr_shade, ssr_trace, ssr_resolve and ssr_shade_backward.  Without it they
+ * are [H][W][spp] int32.  With SSR_CODES_TILED they are tile-major over 8 x 8
+ * pixel tiles: [ceil(H/8) ceil(W/8)][spp][64] int32 (ssr_codes_count
+ * entries), tile (tx, ty) at ty ceil(W/8) + tx, pixel (i, j) at
+ * (j % 8) 8 + i % 8 inside its tile; entries of pixels outside the image are
+ * not written.  The hierarchical trace writes this layout with far less
+ * memory traffic (the rays a wave draws together land in a few cache lines);
+ * ssr_shade uses it for its own workspace when out_hits is NULL.  The codes'
+ * values are the same in both layouts. */
+enum { SSR_CODES_TILED = 8u };
+
 /* Per-sample hit codes written to out_hits (>= 0: hit pixel index j*W + i). */
 enum {
     SSR_HIT_OFFSCREEN = -1,  /* left the screen or the ray segment: env read    */
@@ -133,7 +145,8 @@ typedef struct {
     float thickness;   /* depth slab behind a surface that counts as a hit (>= 0) */
     uint64_t seed;     /* Philox key: (seed mod 2^32, seed >> 32)                 */
     uint32_t frame;    /* third Philox counter word                               */
-    uint32_t flags;    /* SSR_NO_DIRECT | SSR_NO_SPECULAR | SSR_SAMPLER_NDF       */
+    uint32_t flags;    /* SSR_NO_DIRECT | SSR_NO_SPECULAR | SSR_SAMPLER_NDF |
+                          SSR_CODES_TILED                                        */
 } ssr_params;
 
 /* Create a context on HIP device `device` (must be gfx950).  The context owns
@@ -148,9 +161,11 @@ void ssr_ctx_destroy(ssr_ctx* ctx);
 /* Shade one frame (Sec. 3.2 diffuse + Sec. 3.3 Monte-Carlo specular):
  * ssr_trace followed by ssr_resolve on `stream`.
  *   out_rgb   [H][W][3] float32, written: linear HDR c_d + c_s' (no tone map).
- *   out_hits  NULL or [H][W][spp] int32: per-sample hit pixel or SSR_HIT_* code
- *             (NULL: the codes go to the context's workspace).
- *   out_steps NULL or [H][W][spp] int32: march iterations each sample used.
+ *   out_hits  NULL or [H][W][spp] int32 (tile-major with SSR_CODES_TILED):
+ *             per-sample hit pixel or SSR_HIT_* code (NULL: the codes go to
+ *             the context's workspace, tile-major).
+ *   out_steps NULL or int32 in the layout of out_hits: march iterations each
+ *             sample used.
  * Sample s of pixel q = j*W + i draws Philox4x32-10 with counter
  * (q, s, frame, 0): u1 = (x0 >> 8) 2^-24 picks the azimuth, u2 = (x1 >> 8) 2^-24
  * the cap height of the visible-normal sample.  width or height 0 is a no-op;
@@ -163,7 +178,8 @@ int ssr_shade(ssr_ctx* ctx, const ssr_camera* cam, const ssr_gbuffer* gbuf,
               int32_t* out_hits, int32_t* out_steps, void* stream);
 
 /* The march half of ssr_shade (Sec. 3.3 sampling, Appendix D march): write
- * every sample's hit code to out_hits ([H][W][spp] int32, required) and,
+ * every sample's hit code to out_hits ([H][W][spp] int32, or tile-major with
+ * SSR_CODES_TILED; required) and,
  * unless NULL, its iteration count to out_steps.  Reads depth and the
  * normal/roughness buffer (and gbuf->hiz); the other buffers and the
  * environment are not used.  Same validation as ssr_shade. */
@@ -171,7 +187,8 @@ int ssr_trace(ssr_ctx* ctx, const ssr_camera* cam, const ssr_gbuffer* gbuf,
               const ssr_params* params, int32_t* out_hits, int32_t* out_steps, void* stream);
 
 /* The shading half of ssr_shade (Sec. 3.2, Sec. 3.3 estimator): out_rgb from
- * per-sample hit codes `hits` [H][W][spp] int32 (as ssr_trace writes them, or
+ * per-sample hit codes `hits` ([H][W][spp] int32, or tile-major with
+ * SSR_CODES_TILED; as ssr_trace writes them, or
  * any codes to replay).  The sample directions are drawn again from the same
  * Philox counters; a code >= 0 reads the first-pass radiance of that pixel,
  * SSR_HIT_OFFSCREEN and SSR_HIT_CAP the environment along the sample; a code
@@ -182,7 +199,8 @@ int ssr_resolve(ssr_ctx* ctx, const ssr_camera* cam, const ssr_gbuffer* gbuf,
 
 /* The adjoint of ssr_resolve (the shading with the hit selection held fixed;
  * the paper differentiates its shading with the screen-space tracing treated
- * as a fixed selection): given the hit codes `hits` [H][W][spp] of a frame and
+ * as a fixed selection): given the hit codes `hits` of a frame ([H][W][spp],
+ * or tile-major with SSR_CODES_TILED) and
  * the gradient of a loss with respect to its image, grad_rgb [H][W][3], write
  * or accumulate the gradient with respect to the inputs:
  *   g_normal_rough [H][W][4]: written, d/d(n.x, n.y, n.z, rho) of the stored
@@ -206,6 +224,11 @@ int ssr_shade_backward(ssr_ctx* ctx, const ssr_camera* cam, const ssr_gbuffer* g
                        const ssr_env* env, const ssr_params* params, const int32_t* hits,
                        const float* grad_rgb, float* g_normal_rough, float* g_albedo_metal,
                        float* g_env, float* g_radiance, void* stream);
+
+/* Entries of a per-sample buffer (hit codes, iteration counts) of a
+ * width x height frame with spp samples in the layout `flags` selects
+ * (SSR_CODES_TILED or not); 0 for negative sizes. */
+int64_t ssr_codes_count(int32_t width, int32_t height, int32_t spp, uint32_t flags);
 
 /* Number of floats of the env mip-chain buffer for a We x He map (0 if the
  * dimensions are invalid). */

@@ -80,7 +80,8 @@ int check_params(const ssr_params* p) {
     if (!(p->thickness >= 0.0f) || !finite_f(p->thickness)) return SSR_E_ARG;
     if (p->march == SSR_MARCH_LINEAR && (!(p->step_len > 0.0f) || !finite_f(p->step_len)))
         return SSR_E_ARG;
-    if (p->flags & ~static_cast<uint32_t>(SSR_NO_DIRECT | SSR_NO_SPECULAR | SSR_SAMPLER_NDF))
+    if (p->flags & ~static_cast<uint32_t>(SSR_NO_DIRECT | SSR_NO_SPECULAR | SSR_SAMPLER_NDF |
+                                          SSR_CODES_TILED))
         return SSR_E_ARG;
     return SSR_OK;
 }
@@ -217,6 +218,13 @@ void ssr_ctx_destroy(ssr_ctx* ctx) {
         if (ctx->lut) (void)hipFree(ctx->lut);
     }
     delete ctx;
+}
+
+int64_t ssr_codes_count(int32_t width, int32_t height, int32_t spp, uint32_t flags) {
+    if (width < 0 || height < 0 || spp < 0) return 0;
+    if (flags & SSR_CODES_TILED)
+        return static_cast<int64_t>((width + 7) / 8) * ((height + 7) / 8) * 64 * spp;
+    return static_cast<int64_t>(width) * height * spp;
 }
 
 int64_t ssr_env_mips_floats(int32_t width, int32_t height) {
@@ -374,7 +382,10 @@ int ssr_shade(ssr_ctx* ctx, const ssr_camera* cam, const ssr_gbuffer* g, const s
     if (st != SSR_OK) return st;
     int32_t* codes = out_hits;
     if (!codes) {
-        const int64_t n = static_cast<int64_t>(cam->width) * cam->height * p->spp;
+        // the context's own codes go tile-major (unless the caller wants the
+        // iteration counts, which share the codes' layout)
+        if (!out_steps) a.flags |= SSR_CODES_TILED;
+        const int64_t n = ssr_codes_count(cam->width, cam->height, p->spp, a.flags);
         st = ensure(&ctx->codes, &ctx->codes_cap, n);
         if (st != SSR_OK) return st;
         codes = ctx->codes;

@@ -307,7 +307,6 @@ __global__ __launch_bounds__(256) void backward_kernel(const ShadeArgs a, const 
                 if (two) add_env(b, a.env_lay.offset[k1], k1, t1, coef1);
             }
 
-            const int32_t* codes = b.hits + q * S;
             if (P.trace) {
                 const float invS = 1.0f / static_cast<float>(S);
                 // tangent frame and stretched view vector as duals
@@ -321,7 +320,7 @@ __global__ __launch_bounds__(256) void backward_kernel(const ShadeArgs a, const 
                 const Dual a2 = rho * rho;
 #pragma unroll 1
                 for (int s = 0; s < S; ++s) {
-                    int code = codes[s];
+                    int code = b.hits[code_index(a, i, j, s)];
                     if (code >= a.W * a.H || code < SSR_HIT_SKIPPED) code = SSR_HIT_INVALID;
                     if (!(code >= 0 || code == SSR_HIT_OFFSCREEN || code == SSR_HIT_CAP)) continue;
                     const uint4 x = philox4x32_10(

@@ -42,7 +42,7 @@ Workspace workspace_of(const ssr_camera& cam, const ssr_params& p, const ssr::Hi
     w.hiz = kAlign;
     const int64_t hiz_bytes = p.march == SSR_MARCH_HIZ ? round_up(lay.total * 16) : 0;
     w.codes = w.hiz + hiz_bytes;
-    w.total = w.codes + static_cast<int64_t>(cam.width) * cam.height * p.spp * 4;
+    w.total = w.codes + ssr_codes_count(cam.width, cam.height, p.spp, p.flags | SSR_CODES_TILED) * 4;
     return w;
 }
 
@@ -116,6 +116,7 @@ int ssr_session::launch(const ssr::serve::Admitted& ad) {
     a.env = sc.mips;
     a.tile_counter = reinterpret_cast<int*>(ws + w.counter);
     a.codes = reinterpret_cast<int32_t*>(ws + w.codes);
+    a.flags |= SSR_CODES_TILED;  // the request's own codes: tile-major, as ssr_shade's
     a.out = rec.req.out_rgb;
     if (p.march == SSR_MARCH_HIZ) {
         float4* hiz = reinterpret_cast<float4*>(ws + w.hiz);

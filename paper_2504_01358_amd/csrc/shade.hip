@@ -61,8 +61,8 @@ __device__ __forceinline__ MarchResult march_linear(const ShadeArgs& a, int i, i
 // the ray's part inside it lies wholly in front of that union (its smallest
 // inverse depth exceeds the first) or wholly behind it (its largest inverse
 // depth is below the second).  Each iteration looks at the level-L cell and
-// its parent at once (two independent 8 B gathers): skip the parent and go
-// up a level, else skip the cell, else go down two levels, else (level 0)
+// its parent at once (one 16 B texel holds both pairs): skip the parent and
+// go up a level, else skip the cell, else go down two levels, else (level 0)
 // test the pixel and step to the next one.
 //
 // The march is resumable (one iteration per call) so that a wave can keep
@@ -107,8 +107,26 @@ struct HizRay {
     int it;               // iterations so far
 };
 
-__device__ __forceinline__ void hiz_start(const ShadeArgs& a, HizRay& r, int i, int j, float dPx,
-                                          float dPy, float iz0, float diz) {
+// The next pixel after moving to segment parameter se across the boundary
+// of a cell whose exits are ex, ey (crossing at sx, sy): on a crossed axis the
+// first pixel past the boundary, on the other axis the pixel the point lies in.
+__device__ __forceinline__ void next_pixel(const HizRay& r, float se, float sx, float sy, int ex,
+                                           int ey, int& nx, int& ny) {
+    const bool kx = sx == se, ky = sy == se;
+    const int v = static_cast<int>(floorf(fmaf(se, kx ? r.dPy : r.dPx, kx ? r.P0y : r.P0x)));
+    nx = kx ? ex + r.xp - 1 : v;
+    ny = ky ? ey + r.yp - 1 : v;
+}
+
+// Start a ray and take its first iteration.  At s = 0 the ray lies in the
+// slab of its own pixel and of every cell containing it (their nearest depth
+// is at most the pixel's, their farthest depth plus thickness at least its
+// own), so neither the pixel nor its parent can be skipped and the first
+// iteration always crosses the origin pixel into the next one (no test).
+// Returns true when that already ends the ray (it left the segment or the
+// screen, or the cap is one iteration); then `leave` tells which.
+__device__ __forceinline__ bool hiz_start(const ShadeArgs& a, HizRay& r, int i, int j, float dPx,
+                                          float dPy, float iz0, float diz, bool& leave) {
     r.P0x = static_cast<float>(i) + 0.5f;
     r.P0y = static_cast<float>(j) + 0.5f;
     r.dPx = dPx;
@@ -125,13 +143,22 @@ __device__ __forceinline__ void hiz_start(const ShadeArgs& a, HizRay& r, int i, 
                     1.0f);
     r.iz0 = iz0;
     r.diz = diz;
-    r.s = 0.0f;
-    r.iz_in = iz0;
     r.L = 0;
-    r.ix = i;
-    r.iy = j;
     r.armed = false;
-    r.it = 0;
+    r.it = 1;
+    const int ex = i + r.xp, ey = j + r.yp;
+    const float sx = fmaf(static_cast<float>(ex), r.inv_dx, r.bx);
+    const float sy = fmaf(static_cast<float>(ey), r.inv_dy, r.by);
+    const float se = fminf(fminf(sx, sy), r.s_max);
+    int nx, ny;
+    next_pixel(r, se, sx, sy, ex, ey, nx, ny);
+    leave = (se >= r.s_max) | (static_cast<unsigned>(nx) >= static_cast<unsigned>(a.W)) |
+            (static_cast<unsigned>(ny) >= static_cast<unsigned>(a.H));
+    r.ix = nx;
+    r.iy = ny;
+    r.s = se;
+    r.iz_in = fmaf(se, diz, iz0);
+    return leave | (a.max_steps <= 1);
 }
 
 // One iteration, branch-free.  Returns true when the ray is finished; then
@@ -173,22 +200,19 @@ __device__ __forceinline__ bool hiz_step(const ShadeArgs& a, const int2* lvl, Hi
     // outcomes: skip the parent / skip the cell / go down / level-0 pixel
     const bool stay = !up & !skip_c;
     const bool at0 = L == 0;
-    // (the segment starts in the origin pixel, at s = 0, and every move
-    // crosses into another pixel, so it is outside the origin pixel once s > 0)
-    const bool test = stay & at0 & (r.s > 0.0f);
+    // (every ray here has left its origin pixel: its first iteration is
+    // taken when it starts)
+    const bool test = stay & at0;
     hit = test & (r.armed | (r.iz_in > zc.x));
     const bool move = !hit & (!stay | at0);
     // the cell the segment moves across
     const float se = up ? sep : sec;
     const float sx = up ? sxp : sxc, sy = up ? syp : syc;
     const int ex = up ? epx : ecx, ey = up ? epy : ecy;
-    r.armed = r.armed | (move & (up ? front_p : front_c) & !stay & (se > r.s)) | (test & (nc > zc.x));
-    // the pixel on the far side of the crossed boundary: on a crossed axis the
-    // first pixel past it, on the other axis the pixel the point lies in
-    const bool kx = sx == se, ky = sy == se;
-    const int v = static_cast<int>(floorf(fmaf(se, kx ? r.dPy : r.dPx, kx ? r.P0y : r.P0x)));
-    const int nx = kx ? ex + r.xp - 1 : v;
-    const int ny = ky ? ey + r.yp - 1 : v;
+    r.armed = r.armed | (move & (up ? front_p : front_c) & !stay & (se > r.s)) |
+              (test & (nc > zc.x));
+    int nx, ny;
+    next_pixel(r, se, sx, sy, ex, ey, nx, ny);
     leave = move & ((se >= r.s_max) | (static_cast<unsigned>(nx) >= static_cast<unsigned>(a.W)) |
                     (static_cast<unsigned>(ny) >= static_cast<unsigned>(a.H)));
     const bool step = move & !leave;
@@ -206,7 +230,7 @@ __device__ __forceinline__ bool hiz_step(const ShadeArgs& a, const int2* lvl, Hi
 // Workgroups of 256 threads take 16 x 16 pixel tiles; each wave64 an 8 x 8
 // quadrant; each thread marches its pixel's samples in order, in lockstep
 // with the wave, and writes their hit codes.
-template <int DT>
+template <int DT, int TL>
 __global__ __launch_bounds__(256) void trace_linear_kernel(const ShadeArgs a) {
     const int tiles_x = (a.W + 15) / 16;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -227,8 +251,9 @@ __global__ __launch_bounds__(256) void trace_linear_kernel(const ShadeArgs a) {
                 iters = r.iters;
             }
         }
-        a.codes[q * S + s] = code;
-        if (a.steps) a.steps[q * S + s] = iters;
+        const int64_t c = code_index<TL>(a, i, j, s);
+        a.codes[c] = code;
+        if (a.steps) a.steps[c] = iters;
     }
 }
 
@@ -261,7 +286,7 @@ __global__ __launch_bounds__(256) void trace_linear_kernel(const ShadeArgs a) {
 #define SSR_QUEUE_LOW 64
 #endif
 #ifndef SSR_REFILL_MIN
-#define SSR_REFILL_MIN 8
+#define SSR_REFILL_MIN 16
 #endif
 #ifndef SSR_WAVES_PER_EU
 #define SSR_WAVES_PER_EU 5
@@ -276,7 +301,7 @@ static_assert(kQueueLow - 1 + kGenBatch * 64 <= kQueueCap, "ray queue too small"
 
 __global__ void reset_counter_kernel(int* counter) { *counter = 0; }
 
-template <int DT>
+template <int DT, int TL>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(SSR_WAVES_PER_EU, 8)))
 void trace_hiz_kernel(const ShadeArgs a) {
     __shared__ int2 lvl[kMaxLevels];
@@ -305,9 +330,16 @@ void trace_hiz_kernel(const ShadeArgs a) {
     int tile = next_tile();     // tile being drawn (n_tiles or more: none left)
     int kk = 0;                 // its next sample index
     int qh = 0, qt = 0;         // queue head and tail (monotone; slots modulo kQueueCap)
+    int nidle = 64;             // lanes without a ray
     HizRay r;
     int32_t* dst = nullptr;     // where the marching ray's hit code goes
     bool active = false;
+    // a lane's ray ended: write its code (and iteration count)
+    auto finish = [&](bool hit, bool leave) {
+        *dst = hit ? r.iy * a.W + r.ix : (leave ? SSR_HIT_OFFSCREEN : SSR_HIT_CAP);
+        if (a.steps) a.steps[dst - a.codes] = r.it;
+        active = false;
+    };
     for (;;) {
         // draw more rays while the queue runs low
         if (tile < n_tiles && qt - qh < kQueueLow) {
@@ -338,10 +370,10 @@ void trace_hiz_kernel(const ShadeArgs a) {
                     q_seg[pos] = make_float4(sg.dPx, sg.dPy, sg.iz0, sg.diz);
                     q_ray[pos] = make_int2(i | (j << 16), k);
                 } else if (inb) {
-                    a.codes[q * S + k] = code;
-                    if (a.steps) a.steps[q * S + k] = 0;
+                    a.codes[code_index<TL>(a, i, j, k)] = code;
+                    if (a.steps) a.steps[code_index<TL>(a, i, j, k)] = 0;
                 }
-                qt += __popcll(m);
+                qt = __builtin_amdgcn_readfirstlane(qt + __popcll(m));
             }
             kk += g;
             if (kk == S) {
@@ -351,42 +383,45 @@ void trace_hiz_kernel(const ShadeArgs a) {
             __builtin_amdgcn_wave_barrier();
             continue;
         }
-        // march until the queue runs low again (while tiles remain) or drains
-        for (;;) {
+        // refill idle lanes together once enough of them wait (or the queue is shorter)
+        const int rem = qt - qh;
+        if (rem > 0 && nidle >= min(kRefillMin, rem)) {
             const unsigned long long idle = __ballot(!active);
-            const int nidle = __popcll(idle);
-            const int rem = qt - qh;
-            if (rem > 0 && nidle >= min(kRefillMin, rem)) {
-                const int rank = __popcll(idle & below);
-                if (!active && rank < rem) {
-                    const int pos = (qh + rank) & (kQueueCap - 1);
-                    const float4 gq = q_seg[pos];
-                    const int2 ray = q_ray[pos];
-                    const int ri = ray.x & 0xFFFF, rj = ray.x >> 16;
-                    hiz_start(a, r, ri, rj, gq.x, gq.y, gq.z, gq.w);
-                    dst = a.codes + (static_cast<int64_t>(rj) * a.W + ri) * S + ray.y;
-                    active = true;
-                }
-                qh += min(nidle, rem);
+            const int rank = __popcll(idle & below);
+            if (!active && rank < rem) {
+                const int pos = (qh + rank) & (kQueueCap - 1);
+                const float4 gq = q_seg[pos];
+                const int2 ray = q_ray[pos];
+                const int ri = ray.x & 0xFFFF, rj = ray.x >> 16;
+                dst = a.codes + code_index<TL>(a, ri, rj, ray.y);
+                active = true;
+                bool leave;
+                if (hiz_start(a, r, ri, rj, gq.x, gq.y, gq.z, gq.w, leave)) finish(false, leave);
             }
-            if (!__any(active)) break;
+            qh = __builtin_amdgcn_readfirstlane(qh + min(nidle, rem));
+            nidle = __popcll(__ballot(!active));
+        }
+        if (nidle == 64) {
+            if (tile >= n_tiles && qt == qh) break;
+            continue;
+        }
+        // march: one iteration when the queue wants more rays drawn, else until
+        // enough lanes are idle to refill (all of them once nothing is queued)
+        const bool gen = tile < n_tiles && qt - qh < kQueueLow;
+        const int want = qt > qh ? min(kRefillMin, qt - qh) : 64;
+        do {
             if (active) {
                 bool hit, leave;
-                if (hiz_step(a, lvl, r, hit, leave)) {
-                    *dst = hit ? r.iy * a.W + r.ix : (leave ? SSR_HIT_OFFSCREEN : SSR_HIT_CAP);
-                    if (a.steps) a.steps[dst - a.codes] = r.it;
-                    active = false;
-                }
+                if (hiz_step(a, lvl, r, hit, leave)) finish(hit, leave);
             }
-            if (tile < n_tiles && qt - qh < kQueueLow) break;
-        }
+            nidle = __popcll(__ballot(!active));
+        } while (!gen && nidle < want);
         __builtin_amdgcn_wave_barrier();
-        if (tile >= n_tiles && qt == qh && !__any(active)) break;
     }
 }
 
 // Workgroups of 256 threads shade 16 x 16 pixel tiles, one thread per pixel.
-template <int DT>
+template <int DT, int TL>
 __global__ __launch_bounds__(256) void resolve_kernel(const ShadeArgs a) {
     const int tiles_x = (a.W + 15) / 16;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -398,10 +433,9 @@ __global__ __launch_bounds__(256) void resolve_kernel(const ShadeArgs a) {
     const Pixel P = setup_pixel<DT>(a, i, j, q);
     float sum[3] = {0.0f, 0.0f, 0.0f}, cmp[3] = {0.0f, 0.0f, 0.0f};
     if (P.trace) {
-        const int32_t* codes = a.codes + q * S;
 #pragma unroll 1
         for (int s = 0; s < S; ++s) {
-            int code = codes[s];
+            int code = a.codes[code_index<TL>(a, i, j, s)];
             // (a code naming no pixel of this frame contributes nothing)
             if (code >= a.W * a.H || code < SSR_HIT_SKIPPED) code = SSR_HIT_INVALID;
             if (code >= 0 || code == SSR_HIT_OFFSCREEN || code == SSR_HIT_CAP) {
@@ -413,6 +447,20 @@ __global__ __launch_bounds__(256) void resolve_kernel(const ShadeArgs a) {
     write_out(a, q, direct_term(a, P, i, j), sum);
 }
 
+// One instantiation per storage type and per-sample layout.
+#define SSR_DISPATCH(dtype, tiled)                      \
+    do {                                                \
+        if (tiled) {                                    \
+            if ((dtype) == SSR_F32) SSR_LAUNCH(0, 1);   \
+            else if ((dtype) == SSR_F16) SSR_LAUNCH(1, 1); \
+            else SSR_LAUNCH(2, 1);                      \
+        } else {                                        \
+            if ((dtype) == SSR_F32) SSR_LAUNCH(0, 0);   \
+            else if ((dtype) == SSR_F16) SSR_LAUNCH(1, 0); \
+            else SSR_LAUNCH(2, 0);                      \
+        }                                               \
+    } while (0)
+
 int trace_grid(int cu_count, int W, int H) {
     const int n_tiles = ((W + 7) / 8) * ((H + 7) / 8);
     const int resident = cu_count * 4 * kTraceWavesPerEU;
@@ -421,34 +469,34 @@ int trace_grid(int cu_count, int W, int H) {
 
 hipError_t launch_trace(const ShadeArgs& args, int dtype, int march, int cu_count,
                         hipStream_t stream) {
+    const bool tiled = (args.flags & SSR_CODES_TILED) != 0;
     if (march == SSR_MARCH_LINEAR) {
         const dim3 grid(((args.W + 15) / 16) * ((args.H + 15) / 16));
-#define SSR_LAUNCH(DT) \
-    hipLaunchKernelGGL((trace_linear_kernel<DT>), grid, dim3(256), 0, stream, args)
-        if (dtype == SSR_F32) SSR_LAUNCH(0);
-        else if (dtype == SSR_F16) SSR_LAUNCH(1);
-        else SSR_LAUNCH(2);
+#define SSR_LAUNCH(DT, TL) \
+    hipLaunchKernelGGL((trace_linear_kernel<DT, TL>), grid, dim3(256), 0, stream, args)
+        SSR_DISPATCH(dtype, tiled);
 #undef SSR_LAUNCH
         return hipGetLastError();
     }
     hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, stream, args.tile_counter);
     const dim3 grid(trace_grid(cu_count, args.W, args.H));
-#define SSR_LAUNCH(DT) hipLaunchKernelGGL((trace_hiz_kernel<DT>), grid, dim3(64), 0, stream, args)
-    if (dtype == SSR_F32) SSR_LAUNCH(0);
-    else if (dtype == SSR_F16) SSR_LAUNCH(1);
-    else SSR_LAUNCH(2);
+#define SSR_LAUNCH(DT, TL) \
+    hipLaunchKernelGGL((trace_hiz_kernel<DT, TL>), grid, dim3(64), 0, stream, args)
+    SSR_DISPATCH(dtype, tiled);
 #undef SSR_LAUNCH
     return hipGetLastError();
 }
 
 hipError_t launch_resolve(const ShadeArgs& args, int dtype, hipStream_t stream) {
+    const bool tiled = (args.flags & SSR_CODES_TILED) != 0;
     const dim3 grid(((args.W + 15) / 16) * ((args.H + 15) / 16));
-#define SSR_LAUNCH(DT) hipLaunchKernelGGL((resolve_kernel<DT>), grid, dim3(256), 0, stream, args)
-    if (dtype == SSR_F32) SSR_LAUNCH(0);
-    else if (dtype == SSR_F16) SSR_LAUNCH(1);
-    else SSR_LAUNCH(2);
+#define SSR_LAUNCH(DT, TL) \
+    hipLaunchKernelGGL((resolve_kernel<DT, TL>), grid, dim3(256), 0, stream, args)
+    SSR_DISPATCH(dtype, tiled);
 #undef SSR_LAUNCH
     return hipGetLastError();
 }
+
+#undef SSR_DISPATCH
 
 }  // namespace ssr

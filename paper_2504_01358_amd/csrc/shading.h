@@ -216,6 +216,23 @@ __device__ __forceinline__ int fill_code(const ShadeArgs& a, const Pixel& P) {
                 : ((a.flags & SSR_NO_SPECULAR) ? SSR_HIT_SKIPPED : SSR_HIT_INVALID);
 }
 
+// Index of sample k of pixel (i, j) in a per-sample buffer (hit codes,
+// iteration counts): [H][W][S], or with SSR_CODES_TILED tile-major over 8 x 8
+// pixel tiles, [ceil(H/8) ceil(W/8)][S][64] with the pixel at (j % 8) 8 +
+// i % 8 of its tile (a tile's codes of one sample fill 256 contiguous bytes,
+// so the rays a wave draws together write a few cache lines).
+// The hot kernels take the layout as a template argument (TL: 1 tile-major,
+// 0 public, -1 read from the flags at run time).
+template <int TL = -1>
+__device__ __forceinline__ int64_t code_index(const ShadeArgs& a, int i, int j, int k) {
+    const bool tiled = TL < 0 ? (a.flags & SSR_CODES_TILED) != 0 : TL == 1;
+    if (tiled) {
+        const int t = (j >> 3) * ((a.W + 7) >> 3) + (i >> 3);
+        return (static_cast<int64_t>(t) * a.spp + k) * 64 + ((j & 7) << 3) + (i & 7);
+    }
+    return (static_cast<int64_t>(j) * a.W + i) * a.spp + k;
+}
+
 __device__ __forceinline__ void write_out(const ShadeArgs& a, int64_t q, float3 cd, const float* sum) {
     const float invS = 1.0f / static_cast<float>(a.spp);
     // one 12-byte store per pixel: a row of lanes writes one contiguous run

@@ -26,9 +26,18 @@ SYMBOLS = ("ssr_ctx_create", "ssr_ctx_destroy", "ssr_shade", "ssr_trace", "ssr_r
            "ssr_philox4x32_10", "ssr_status_string", "ssr_session_create",
            "ssr_session_add_scene", "ssr_session_request_bytes", "ssr_session_submit",
            "ssr_session_poll", "ssr_session_wait", "ssr_session_get_stats",
-           "ssr_session_destroy", "ssr_depth_normals", "ssr_brdf_lut", "ssr_first_pass")
+           "ssr_session_destroy", "ssr_depth_normals", "ssr_brdf_lut", "ssr_first_pass", "ssr_codes_count")
 
 PENDING = 1
+CODES_TILED = 8      # per-sample buffers tile-major over 8 x 8 pixel tiles
+
+
+def codes_shape(width, height, spp, flags=0):
+    """Shape of a per-sample buffer (hit codes, iteration counts): (H, W, spp),
+    or (ceil(H/8) ceil(W/8), spp, 64) with CODES_TILED."""
+    if int(flags) & CODES_TILED:
+        return (((int(height) + 7) // 8) * ((int(width) + 7) // 8), int(spp), 64)
+    return (int(height), int(width), int(spp))
 
 
 class SSRError(RuntimeError):
@@ -134,6 +143,8 @@ def _load():
     lib.ssr_brdf_lut.restype = ctypes.c_int
     lib.ssr_first_pass.argtypes = [vp, P(Camera), P(GBuffer), P(Env), vp, vp]
     lib.ssr_first_pass.restype = ctypes.c_int
+    lib.ssr_codes_count.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint32]
+    lib.ssr_codes_count.restype = ctypes.c_int64
     lib.ssr_status_string.argtypes = [ctypes.c_int]
     lib.ssr_status_string.restype = ctypes.c_char_p
     return lib
@@ -267,7 +278,7 @@ class Context:
         out = self._out(out, cam, depth.device)
         for name, t in (("hits", hits), ("steps", steps)):
             if t is not None:
-                _dev_tensor(t, name, torch.int32, (cam.height, cam.width, prm.spp))
+                _dev_tensor(t, name, torch.int32, codes_shape(cam.width, cam.height, prm.spp, prm.flags))
         st = lib.ssr_shade(self._h, ctypes.byref(cam), ctypes.byref(g), ctypes.byref(e),
                            ctypes.byref(prm), _ptr(out), _ptr(hits), _ptr(steps),
                            _stream(stream, depth.device))
@@ -282,11 +293,11 @@ class Context:
         prm = params if isinstance(params, Params) else make_params(params)
         g = self._gbuf(cam, depth, normal_rough, albedo_metal, radiance, hiz)
         if hits is None:
-            hits = torch.empty((cam.height, cam.width, prm.spp), dtype=torch.int32,
+            hits = torch.empty(codes_shape(cam.width, cam.height, prm.spp, prm.flags), dtype=torch.int32,
                                device=depth.device)
         for name, t in (("hits", hits), ("steps", steps)):
             if t is not None:
-                _dev_tensor(t, name, torch.int32, (cam.height, cam.width, prm.spp))
+                _dev_tensor(t, name, torch.int32, codes_shape(cam.width, cam.height, prm.spp, prm.flags))
         st = lib.ssr_trace(self._h, ctypes.byref(cam), ctypes.byref(g), ctypes.byref(prm),
                            _ptr(hits), _ptr(steps), _stream(stream, depth.device))
         _check(st, "ssr_trace")
@@ -300,7 +311,7 @@ class Context:
         g = self._gbuf(cam, depth, normal_rough, albedo_metal, radiance, None)
         e = self._env(env, env_mips)
         out = self._out(out, cam, depth.device)
-        _dev_tensor(hits, "hits", torch.int32, (cam.height, cam.width, prm.spp))
+        _dev_tensor(hits, "hits", torch.int32, codes_shape(cam.width, cam.height, prm.spp, prm.flags))
         st = lib.ssr_resolve(self._h, ctypes.byref(cam), ctypes.byref(g), ctypes.byref(e),
                              ctypes.byref(prm), _ptr(hits), _ptr(out),
                              _stream(stream, depth.device))
@@ -320,7 +331,7 @@ def _shade_backward(self, camera, depth, normal_rough, albedo_metal, radiance, e
     g = Context._gbuf(cam, depth, normal_rough, albedo_metal, radiance, None)
     e = Context._env(env, env_mips)
     H, W = cam.height, cam.width
-    _dev_tensor(hits, "hits", torch.int32, (H, W, prm.spp))
+    _dev_tensor(hits, "hits", torch.int32, codes_shape(W, H, prm.spp, prm.flags))
     _dev_tensor(grad_rgb, "grad_rgb", torch.float32, (H, W, 3))
     for name, t, shape in (("g_normal_rough", g_normal_rough, (H, W, 4)),
                            ("g_albedo_metal", g_albedo_metal, (H, W, 4)),

@@ -36,7 +36,7 @@ def declared_functions():
 
 def test_every_declared_symbol_is_exported(lib):
     names = declared_functions()
-    assert len(names) == 23, names
+    assert len(names) == 24, names
     raw = ctypes.CDLL(LIB)
     for n in names:
         assert hasattr(raw, n), n
@@ -102,6 +102,17 @@ def test_sizes_and_status_strings(lib):
     for s in (0, -1, -2, -3, -4, -5):
         assert lib.status_string(s) and lib.status_string(s) != "unknown status"
     assert lib.status_string(-99) == "unknown status"
+
+
+def test_codes_count(lib):
+    raw = lib.lib
+    assert raw.ssr_codes_count(1920, 1080, 16, 0) == 1920 * 1080 * 16
+    assert raw.ssr_codes_count(1920, 1080, 16, lib.CODES_TILED) == 240 * 135 * 64 * 16
+    assert raw.ssr_codes_count(203, 117, 4, lib.CODES_TILED) == 26 * 15 * 64 * 4
+    assert raw.ssr_codes_count(0, 5, 4, lib.CODES_TILED) == 0
+    assert raw.ssr_codes_count(-1, 5, 4, 0) == 0
+    assert lib.codes_shape(203, 117, 4, lib.CODES_TILED) == (26 * 15, 4, 64)
+    assert lib.codes_shape(203, 117, 4) == (117, 203, 4)
 
 
 def test_host_side_argument_checks(lib):

@@ -330,6 +330,57 @@ def test_resolve_replays_oracle_hits(ctx, dtype):
     assert stats["frac_within_1e4"] >= 0.99, stats
 
 
+def _untile(t, W, H):
+    """Tile-major per-sample buffer [tiles][S][64] -> [H][W][S]."""
+    ty, tx = (H + 7) // 8, (W + 7) // 8
+    S = t.shape[1]
+    x = t.reshape(ty, tx, S, 8, 8).transpose(0, 3, 1, 4, 2).reshape(ty * 8, tx * 8, S)
+    return x[:H, :W]
+
+
+@pytest.mark.parametrize("march", ["hiz", "linear"])
+def test_tiled_codes_equal_the_public_layout(ctx, march):
+    """SSR_CODES_TILED only moves the per-sample codes and counts: the same
+    values in the tile-major layout, the same images from trace + resolve, and
+    ssr_shade with its own (tile-major) workspace equals ssr_shade writing the
+    public layout, bit for bit."""
+    from paper_2504_01358_amd import ssr
+    sc = scenes.make_scene("c2", seed=14, width=203, height=117)
+    p = dict(sc.params, spp=4, seed=5)
+    if march == "linear":
+        p.update(march=0, max_steps=32, max_dist=4.0)
+    pt = dict(p, flags=ssr.CODES_TILED)
+    dev = torch.device("cuda", 0)
+    t = {k: torch.from_numpy(getattr(sc, k)).to(dev)
+         for k in ("depth", "normal_rough", "albedo_metal", "radiance", "env")}
+    args = (sc.camera, t["depth"], t["normal_rough"], t["albedo_metal"], t["radiance"])
+    steps = torch.full((117, 203, 4), -9, dtype=torch.int32, device=dev)
+    hits = ctx.trace(*args, p, steps=steps)
+    steps_t = torch.full(ssr.codes_shape(203, 117, 4, ssr.CODES_TILED), -9, dtype=torch.int32,
+                         device=dev)
+    hits_t = ctx.trace(*args, pt, steps=steps_t)
+    torch.cuda.synchronize()
+    assert np.array_equal(_untile(hits_t.cpu().numpy(), 203, 117), hits.cpu().numpy())
+    assert np.array_equal(_untile(steps_t.cpu().numpy(), 203, 117), steps.cpu().numpy())
+    out = ctx.resolve(*args, t["env"], p, hits)
+    out_t = ctx.resolve(*args, t["env"], pt, hits_t)
+    shaded = ctx.shade(*args, t["env"], p)                   # own workspace, tile-major
+    shaded_pub = ctx.shade(*args, t["env"], p, hits=torch.empty_like(hits))
+    torch.cuda.synchronize()
+    assert torch.equal(out, out_t) and torch.equal(out, shaded) and torch.equal(out, shaded_pub)
+    if march == "hiz":
+        g = torch.randn((117, 203, 3), device=dev)
+        grads = []
+        for prm, h in ((p, hits), (pt, hits_t)):
+            gnr = torch.empty((117, 203, 4), device=dev)
+            genv = torch.zeros_like(t["env"])
+            ctx.shade_backward(*args, t["env"], prm, h, g, g_normal_rough=gnr, g_env=genv)
+            grads.append((gnr, genv))
+        torch.cuda.synchronize()
+        assert torch.equal(grads[0][0], grads[1][0])
+        assert torch.allclose(grads[0][1], grads[1][1], rtol=1e-5, atol=1e-6)
+
+
 def test_resolve_treats_foreign_codes_as_invalid(ctx):
     """Codes naming no pixel of the frame (>= W H, or below the smallest code)
     contribute nothing, exactly as SSR_HIT_INVALID does."""
@@ -405,7 +456,7 @@ def test_argument_errors(ctx):
          for k in ("depth", "normal_rough", "albedo_metal", "radiance", "env")}
     args = (sc.camera, t["depth"], t["normal_rough"], t["albedo_metal"], t["radiance"], t["env"])
     for bad in (dict(spp=0), dict(march=7), dict(max_steps=0), dict(step_len=0.0),
-                dict(max_dist=-1.0), dict(thickness=float("nan")), dict(flags=8), dict(flags=16)):
+                dict(max_dist=-1.0), dict(thickness=float("nan")), dict(flags=16), dict(flags=32)):
         with pytest.raises(ssr.SSRError):
             ctx.shade(*args, dict(sc.params, **bad))
     with pytest.raises(ssr.SSRError):
