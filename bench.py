@@ -349,18 +349,19 @@ def time_first_pass(ctx, scene, dev, reps=50):
     res = {}
     for dt in ("f32", "f16"):
         t = upload(scene, dt, dev)
+        mips = ssr.env_build_mips(t["env"], stream=stream)   # built once, as for the shading
         esz = 4 if dt == "f32" else 2
         nr = t["normal_rough"].clone()
         out = torch.empty_like(t["normal_rough"])
         ssr.depth_normals(cam, t["depth"], nr, stream=stream)          # first call: table
-        ctx.first_pass(cam, t["depth"], t["normal_rough"], t["albedo_metal"], t["env"], out=out,
-                       stream=stream)
+        ctx.first_pass(cam, t["depth"], t["normal_rough"], t["albedo_metal"], t["env"], env_mips=mips,
+                       out=out, stream=stream)
         for name, fn, per_px in (
                 ("depth_normals", lambda: ssr.depth_normals(cam, t["depth"], nr, stream=stream),
                  4 + 3 * esz),
                 ("first_pass", lambda: ctx.first_pass(cam, t["depth"], t["normal_rough"],
-                                                      t["albedo_metal"], t["env"], out=out,
-                                                      stream=stream),
+                                                      t["albedo_metal"], t["env"], env_mips=mips,
+                                                      out=out, stream=stream),
                  4 + 3 * 4 * esz)):
             for _ in range(3):
                 fn()
