@@ -59,7 +59,9 @@ __device__ __forceinline__ V3 operator-(V3 a, V3 b) { return v3(a.x - b.x, a.y -
 __device__ __forceinline__ V3 operator*(float s, V3 a) { return v3(s * a.x, s * a.y, s * a.z); }
 __device__ __forceinline__ float dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
 __device__ __forceinline__ V3 normalize(V3 a) {
-    const float inv = 1.0f / sqrtf(dot(a, a));
+    // hardware reciprocal square root (about 1 ulp): the scale of a direction,
+    // whose error does not turn it
+    const float inv = __builtin_amdgcn_rsqf(dot(a, a));
     return inv * a;
 }
 
@@ -120,7 +122,7 @@ struct EnvAngles {
 
 __device__ __forceinline__ EnvAngles env_angles(V3 d) {
     const bool front = d.z > 0.0f, low = d.y < 0.0f;
-    const float r = sqrtf(d.x * d.x + d.z * d.z);
+    const float r = __builtin_amdgcn_sqrtf(d.x * d.x + d.z * d.z);
     return EnvAngles{front ? -atan2f(d.x, d.z) : atan2f(d.x, -d.z),
                      low ? -atan2f(r, -d.y) : atan2f(r, d.y), front, low};
 }
@@ -176,7 +178,8 @@ __device__ __forceinline__ void kahan_add(float& sum, float& comp, float v) {
 // GGX with alpha = rho (Appendix B as written).
 // ----------------------------------------------------------------------------
 __device__ __forceinline__ float smith_g1(float z, float a2) {
-    return 2.0f * z / (z + sqrtf(a2 + (1.0f - a2) * z * z));
+    // (hardware square root and reciprocal, about 1 ulp each)
+    return 2.0f * z * __builtin_amdgcn_rcpf(z + __builtin_amdgcn_sqrtf(a2 + (1.0f - a2) * z * z));
 }
 
 // Branchless tangent frame (Duff et al., JCGT 2017); sign(+0) = +1.

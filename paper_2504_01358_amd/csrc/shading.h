@@ -155,9 +155,9 @@ __device__ __forceinline__ SampleDir sample_dir(const ShadeArgs& a, const Pixel&
         // distribution of normals: cos^2 theta = (1 - u2) / den and
         // sin^2 theta = rho^2 u2 / den, den = 1 + (rho^2 - 1) u2 (no cancellation)
         const float a2 = P.rho * P.rho;
-        const float inv = 1.0f / (1.0f + (a2 - 1.0f) * u2);
-        const float ct = sqrtf((1.0f - u2) * inv);
-        const float st = P.rho * sqrtf(u2 * inv);
+        const float inv = __builtin_amdgcn_rcpf(1.0f + (a2 - 1.0f) * u2);
+        const float ct = __builtin_amdgcn_sqrtf((1.0f - u2) * inv);
+        const float st = P.rho * __builtin_amdgcn_sqrtf(u2 * inv);
         hl = v3(st * cphi, st * sphi, ct);
     } else {
         // visible normals: point on the spherical cap z > -ws.z, azimuth
@@ -168,7 +168,7 @@ __device__ __forceinline__ SampleDir sample_dir(const ShadeArgs& a, const Pixel&
         const float opz = 1.0f + P.ws.z;
         const float hz = one_m_u2 * opz;
         const float sin2 = (u2 * opz) * (hz + (1.0f - P.ws.z));
-        const float st = sqrtf(fmaxf(sin2, 0.0f));
+        const float st = __builtin_amdgcn_sqrtf(fmaxf(sin2, 0.0f));
         hl = normalize(v3(P.rho * (st * cphi + P.ws.x), P.rho * (st * sphi + P.ws.y), hz));
     }
     const V3 h = v3(hl.x * P.t.x + hl.y * P.b.x + hl.z * P.n.x,
