@@ -328,7 +328,7 @@ __global__ __launch_bounds__(256) void backward_kernel(const ShadeArgs a, const 
                         a.key0, a.key1);
                     const float u1 = unit24(x.x), u2 = unit24(x.y);
                     float sphi, cphi;
-                    sincospif(2.0f * u1, &sphi, &cphi);
+                    sincos_rev(u1, &sphi, &cphi);
                     // the visible-normal sample, as in the forward (sample_dir)
                     const Dual opz = 1.0f + ws.z;
                     const Dual hz = (1.0f - u2) * opz;

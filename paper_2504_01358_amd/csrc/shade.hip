@@ -290,6 +290,9 @@ __global__ __launch_bounds__(256) void trace_linear_kernel(const ShadeArgs a) {
 #ifndef SSR_REFILL_MIN
 #define SSR_REFILL_MIN 16
 #endif
+#ifndef SSR_STEP_UNROLL
+#define SSR_STEP_UNROLL 6
+#endif
 #ifndef SSR_WAVES_PER_EU
 #define SSR_WAVES_PER_EU 5
 #endif
@@ -297,6 +300,7 @@ constexpr int kGenBatch = SSR_GEN_BATCH;   // sample indices drawn at once
 constexpr int kQueueLow = SSR_QUEUE_LOW;   // draw when fewer rays than this wait
 constexpr int kRefillMin = SSR_REFILL_MIN;
 constexpr int kTraceWavesPerEU = SSR_WAVES_PER_EU;
+constexpr int kStepUnroll = SSR_STEP_UNROLL;   // march iterations between idle counts
 // the queue never holds more than kQueueLow - 1 + kGenBatch * 64 rays
 constexpr int kQueueCap = 256;
 static_assert(kQueueLow - 1 + kGenBatch * 64 <= kQueueCap, "ray queue too small");
@@ -407,14 +411,19 @@ void trace_hiz_kernel(const ShadeArgs a) {
             if (tile >= n_tiles && qt == qh) break;
             continue;
         }
-        // march: one iteration when the queue wants more rays drawn, else until
+        // march: one round when the queue wants more rays drawn, else until
         // enough lanes are idle to refill (all of them once nothing is queued)
         const bool gen = tile < n_tiles && qt - qh < kQueueLow;
         const int want = qt > qh ? min(kRefillMin, qt - qh) : 64;
+        // (kStepUnroll iterations between two counts of the idle lanes: the
+        // count and the loop test cost as much as a fifth of an iteration)
         do {
-            if (active) {
-                bool hit, leave;
-                if (hiz_step(a, lvl, r, hit, leave)) finish(hit, leave);
+#pragma unroll
+            for (int u = 0; u < kStepUnroll; ++u) {
+                if (active) {
+                    bool hit, leave;
+                    if (hiz_step(a, lvl, r, hit, leave)) finish(hit, leave);
+                }
             }
             nidle = __popcll(__ballot(!active));
         } while (!gen && nidle < want);

@@ -148,7 +148,7 @@ __device__ __forceinline__ SampleDir sample_dir(const ShadeArgs& a, const Pixel&
         make_uint4(static_cast<uint32_t>(q), static_cast<uint32_t>(s), a.frame, 0u), a.key0, a.key1);
     const float u1 = unit24(x.x), u2 = unit24(x.y);
     float sphi, cphi;
-    sincospif(2.0f * u1, &sphi, &cphi);
+    sincos_rev(u1, &sphi, &cphi);
     V3 hl;
     const bool ndf = a.flags & SSR_SAMPLER_NDF;
     if (ndf) {

@@ -29,10 +29,20 @@ def gbuf_of(scene):
                 albedo_metal=scene.albedo_metal, radiance=scene.radiance)
 
 
+def untile(t, W, H):
+    """Tile-major per-sample buffer [ceil(H/8) ceil(W/8)][S][64] -> [H][W][S]."""
+    ty, tx = (H + 7) // 8, (W + 7) // 8
+    S = t.shape[1]
+    x = t.reshape(ty, tx, S, 8, 8).transpose(0, 3, 1, 4, 2).reshape(ty * 8, tx * 8, S)
+    return x[:H, :W]
+
+
 def run_gpu(ctx, cam, g, env, params, dtype="f32", want_hits=True, want_steps=True,
-            env_mips=None, hiz=None):
+            env_mips=None, hiz=None, tiled=False):
     """Shade on cuda:0.  Returns numpy out/hits/steps and the G-buffer values
-    the GPU actually read (quantised for f16/bf16)."""
+    the GPU actually read (quantised for f16/bf16).  With ``tiled`` the frame
+    is traced and resolved with tile-major codes (the launch configuration the
+    benchmark times) and the codes are returned in [H][W][S]."""
     dev = torch.device("cuda", 0)
     W, H, S = int(cam["width"]), int(cam["height"]), int(params["spp"])
     depth = torch.from_numpy(np.ascontiguousarray(g["depth"], np.float32)).to(dev)
@@ -52,6 +62,21 @@ def run_gpu(ctx, cam, g, env, params, dtype="f32", want_hits=True, want_steps=Tr
         bufs = {k: torch.from_numpy(bits[k].view(np.int16)).to(dev).view(tdt) for k in BUFS}
         seen.update(vals)
     envt = torch.from_numpy(np.ascontiguousarray(env, np.float32)).to(dev)
+    if tiled:
+        from paper_2504_01358_amd import ssr
+        pt = dict(params, flags=int(params.get("flags", 0)) | ssr.CODES_TILED)
+        shape = ssr.codes_shape(W, H, S, ssr.CODES_TILED)
+        hits = torch.full(shape, -99, dtype=torch.int32, device=dev)
+        steps = torch.full(shape, -99, dtype=torch.int32, device=dev) if want_steps else None
+        args = (cam, depth, bufs["normal_rough"], bufs["albedo_metal"], bufs["radiance"])
+        ctx.trace(*args, pt, hiz=hiz, hits=hits, steps=steps)
+        out = ctx.resolve(*args, envt, pt, hits, env_mips=env_mips)
+        torch.cuda.synchronize()
+        res = dict(out=out.cpu().numpy().astype(np.float64),
+                   hits=untile(hits.cpu().numpy(), W, H).astype(np.int64))
+        if want_steps:
+            res["steps"] = untile(steps.cpu().numpy(), W, H).astype(np.int64)
+        return res, seen
     hits = torch.full((H, W, S), -99, dtype=torch.int32, device=dev) if want_hits else None
     steps = torch.full((H, W, S), -99, dtype=torch.int32, device=dev) if want_steps else None
     out = ctx.shade(cam, depth, bufs["normal_rough"], bufs["albedo_metal"], bufs["radiance"],

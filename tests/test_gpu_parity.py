@@ -18,7 +18,7 @@ import oracle
 import scenes
 from closed_form import floor_wall_scene, open_floor
 from gpu_util import (DIR_EPS, compare, f32_camera, f32_gbuf, gbuf_of, oracle_frame, rel_err,
-                      run_gpu)
+                      run_gpu, untile)
 
 pytestmark = pytest.mark.gpu
 
@@ -130,17 +130,17 @@ def test_c1_full_frame_parity(ctx):
     _check(_cmp(gpu, ref, "c1"), gpu, ref)
 
 
-@pytest.mark.parametrize("march", ["linear", "hiz"])
-def test_ragged_multi_tile_parity(ctx, march):
+@pytest.mark.parametrize("march,tiled", [("linear", False), ("hiz", False), ("hiz", True)])
+def test_ragged_multi_tile_parity(ctx, march, tiled):
     """Several 16x16 tiles plus ragged edges, 4 spp, the dense 1080p scene's
-    object mix and high-contrast environment."""
+    object mix and high-contrast environment (also with tile-major codes)."""
     kw = dict(width=203, height=117, spp=4, march=march)
     if march == "linear":
         kw.update(max_steps=32, max_dist=4.0)
     sc = scenes.make_scene("c2", **kw)
-    gpu, seen = run_gpu(ctx, sc.camera, gbuf_of(sc), sc.env, sc.params)
+    gpu, seen = run_gpu(ctx, sc.camera, gbuf_of(sc), sc.env, sc.params, tiled=tiled)
     ref = oracle_frame(sc.camera, seen, sc.env, sc.params)
-    _check(_cmp(gpu, ref, f"ragged-{march}"), gpu, ref)
+    _check(_cmp(gpu, ref, f"ragged-{march}{'-tiled' if tiled else ''}"), gpu, ref)
 
 
 def test_c2_1080p_sampled_parity(ctx):
@@ -148,7 +148,7 @@ def test_c2_1080p_sampled_parity(ctx):
     the launch configuration the bench times; the oracle shades a seeded
     sample of pixels one by one."""
     sc = scenes.make_scene("c2")
-    gpu, seen = run_gpu(ctx, sc.camera, gbuf_of(sc), sc.env, sc.params)
+    gpu, seen = run_gpu(ctx, sc.camera, gbuf_of(sc), sc.env, sc.params, tiled=True)
     rng = np.random.default_rng(123)
     pix = rng.choice(sc.width * sc.height, 4096, replace=False)
     ref = oracle.shade_pixels(sc.camera, seen, sc.env, sc.params, pix, sensitivity=DIR_EPS)
@@ -330,14 +330,6 @@ def test_resolve_replays_oracle_hits(ctx, dtype):
     assert stats["frac_within_1e4"] >= 0.99, stats
 
 
-def _untile(t, W, H):
-    """Tile-major per-sample buffer [tiles][S][64] -> [H][W][S]."""
-    ty, tx = (H + 7) // 8, (W + 7) // 8
-    S = t.shape[1]
-    x = t.reshape(ty, tx, S, 8, 8).transpose(0, 3, 1, 4, 2).reshape(ty * 8, tx * 8, S)
-    return x[:H, :W]
-
-
 @pytest.mark.parametrize("march", ["hiz", "linear"])
 def test_tiled_codes_equal_the_public_layout(ctx, march):
     """SSR_CODES_TILED only moves the per-sample codes and counts: the same
@@ -360,8 +352,8 @@ def test_tiled_codes_equal_the_public_layout(ctx, march):
                          device=dev)
     hits_t = ctx.trace(*args, pt, steps=steps_t)
     torch.cuda.synchronize()
-    assert np.array_equal(_untile(hits_t.cpu().numpy(), 203, 117), hits.cpu().numpy())
-    assert np.array_equal(_untile(steps_t.cpu().numpy(), 203, 117), steps.cpu().numpy())
+    assert np.array_equal(untile(hits_t.cpu().numpy(), 203, 117), hits.cpu().numpy())
+    assert np.array_equal(untile(steps_t.cpu().numpy(), 203, 117), steps.cpu().numpy())
     out = ctx.resolve(*args, t["env"], p, hits)
     out_t = ctx.resolve(*args, t["env"], pt, hits_t)
     shaded = ctx.shade(*args, t["env"], p)                   # own workspace, tile-major
