@@ -105,7 +105,8 @@ struct HizRay {
     float iz0, diz;
     float s, iz_in;       // current point of the segment and the ray's inverse depth there
     int L, ix, iy;        // level and the level-0 pixel containing the current point
-    bool armed;           // the ray has been in front of the depth buffer
+    float armed;          // 1 once the ray has been in front of the depth buffer, else 0
+                          // (a float: its tests compile to compares, not byte logic)
     int it;               // iterations so far
 };
 
@@ -146,7 +147,7 @@ __device__ __forceinline__ bool hiz_start(const ShadeArgs& a, HizRay& r, int i, 
     r.iz0 = iz0;
     r.diz = diz;
     r.L = 0;
-    r.armed = false;
+    r.armed = 0.0f;
     r.it = 1;
     const int ex = i + r.xp, ey = j + r.yp;
     const float sx = fmaf(static_cast<float>(ex), r.inv_dx, r.bx);
@@ -205,14 +206,17 @@ __device__ __forceinline__ bool hiz_step(const ShadeArgs& a, const int2* lvl, Hi
     // (every ray here has left its origin pixel: its first iteration is
     // taken when it starts)
     const bool test = stay & at0;
-    hit = test & (r.armed | (r.iz_in > zc.x));
+    const bool was_armed = r.armed > 0.0f;
+    hit = test & (was_armed | (r.iz_in > zc.x));
     const bool move = !hit & (!stay | at0);
     // the cell the segment moves across
     const float se = up ? sep : sec;
     const float sx = up ? sxp : sxc, sy = up ? syp : syc;
     const int ex = up ? epx : ecx, ey = up ? epy : ecy;
-    r.armed = r.armed | (move & (up ? front_p : front_c) & !stay & (se > r.s)) |
-              (test & (nc > zc.x));
+    // (a skip is never a hit, so move & !stay is !stay; a skipped cell was
+    // in front when its own test says so)
+    const bool arm = (((up & front_p) | (!up & front_c)) & (se > r.s)) | (test & (nc > zc.x));
+    r.armed = arm ? 1.0f : r.armed;
     int nx, ny;
     next_pixel(r, se, sx, sy, ex, ey, nx, ny);
     leave = move & ((se >= r.s_max) | (static_cast<unsigned>(nx) >= static_cast<unsigned>(a.W)) |
