@@ -128,11 +128,33 @@ struct EnvAngles {
     bool front, low;   // d.z > 0 (from the seam), d.y < 0 (from the lower pole)
 };
 
+// atan2(a, b) for b >= 0 (including b = -0), without branches: with
+// t = min(|a|, b) / max(|a|, b) in [0, 1], atan(t) = t q(t^2), q the
+// degree-9 polynomial fitted (least squares on Chebyshev nodes) to atan(t)/t,
+// max error 2e-9 (1e-7 once evaluated in float32); pi/2 - atan(t) when
+// |a| > b; the signs of zero follow IEEE atan2 (atan2(+-0, -0) = +-pi).
+__device__ __forceinline__ float atan2_right(float a, float b) {
+    constexpr float kC[10] = {1.0f,           -0.33333284f,  0.19998230f,   -0.14261574f,
+                              0.10940199f,    -0.083720639f, 0.057463557f,  -0.030717509f,
+                              0.010680719f,   -0.0017437012f};
+    const float aa = fabsf(a);
+    const float mx = fmaxf(aa, b), mn = fminf(aa, b);
+    const float t = mx > 0.0f ? mn * __builtin_amdgcn_rcpf(mx) : 0.0f;
+    const float u = t * t;
+    float q = kC[9];
+#pragma unroll
+    for (int k = 8; k >= 0; --k) q = fmaf(q, u, kC[k]);
+    float p = t * q;
+    p = aa > b ? 1.57079633f - p : p;
+    p = (mx == 0.0f && signbit(b)) ? 3.14159265f : p;
+    return copysignf(p, a);
+}
+
 __device__ __forceinline__ EnvAngles env_angles(V3 d) {
     const bool front = d.z > 0.0f, low = d.y < 0.0f;
     const float r = __builtin_amdgcn_sqrtf(d.x * d.x + d.z * d.z);
-    return EnvAngles{front ? -atan2f(d.x, d.z) : atan2f(d.x, -d.z),
-                     low ? -atan2f(r, -d.y) : atan2f(r, d.y), front, low};
+    return EnvAngles{front ? -atan2_right(d.x, d.z) : atan2_right(d.x, -d.z),
+                     low ? -atan2_right(r, -d.y) : atan2_right(r, d.y), front, low};
 }
 
 // 1/(2 pi) and 1/pi as float-float pairs (hi + lo to ~1e-15).
