@@ -286,13 +286,13 @@ __global__ __launch_bounds__(256) void trace_linear_kernel(const ShadeArgs a) {
 // weight x radiance in sample order (Kahan), reading each sample's hit code,
 // so the result does not depend on which lane marched which ray.
 #ifndef SSR_GEN_BATCH
-#define SSR_GEN_BATCH 2
+#define SSR_GEN_BATCH 3
 #endif
 #ifndef SSR_QUEUE_LOW
 #define SSR_QUEUE_LOW 64
 #endif
 #ifndef SSR_REFILL_MIN
-#define SSR_REFILL_MIN 16
+#define SSR_REFILL_MIN 24
 #endif
 #ifndef SSR_STEP_UNROLL
 #define SSR_STEP_UNROLL 6
