@@ -448,14 +448,21 @@ __global__ __launch_bounds__(256) void resolve_kernel(const ShadeArgs a) {
     const Pixel P = setup_pixel<DT>(a, i, j, q);
     float sum[3] = {0.0f, 0.0f, 0.0f}, cmp[3] = {0.0f, 0.0f, 0.0f};
     if (P.trace) {
+        // the next sample's code is loaded one sample ahead, and a hit's
+        // radiance before its direction is drawn again, so that both loads
+        // overlap arithmetic
+        int next = a.codes[code_index<TL>(a, i, j, 0)];
 #pragma unroll 1
         for (int s = 0; s < S; ++s) {
-            int code = a.codes[code_index<TL>(a, i, j, s)];
+            int code = next;
+            if (s + 1 < S) next = a.codes[code_index<TL>(a, i, j, s + 1)];
             // (a code naming no pixel of this frame contributes nothing)
             if (code >= a.W * a.H || code < SSR_HIT_SKIPPED) code = SSR_HIT_INVALID;
             if (code >= 0 || code == SSR_HIT_OFFSCREEN || code == SSR_HIT_CAP) {
+                const float4 c1 = code >= 0 ? Texel4<DT>::load(a.radiance, code)
+                                            : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
                 const SampleDir d = sample_dir(a, P, q, s);
-                accumulate<DT>(a, P, d, code, sum, cmp);
+                accumulate(a, P, d, code, c1, sum, cmp);
             }
         }
     }

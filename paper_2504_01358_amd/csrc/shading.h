@@ -185,14 +185,12 @@ __device__ __forceinline__ SampleDir sample_dir(const ShadeArgs& a, const Pixel&
 }
 
 // Weight F(wo.h) G1(n.l) (visible normals; NDF sampling: the weight above)
-// times the radiance found (c1 at a hit pixel, the
-// unfiltered environment otherwise), Kahan-accumulated per channel.
-template <int DT>
+// times the radiance found (c1 at a hit pixel, loaded by the caller into
+// `c1`, the unfiltered environment otherwise), Kahan-accumulated per channel.
 __device__ __forceinline__ void accumulate(const ShadeArgs& a, const Pixel& P, const SampleDir& d,
-                                           int code, float* sum, float* cmp) {
+                                           int code, float4 c1, float* sum, float* cmp) {
     float3 Lr;
     if (code >= 0) {
-        const float4 c1 = Texel4<DT>::load(a.radiance, code);
         Lr = make_float3(c1.x, c1.y, c1.z);
     } else {
         Lr = env_bilinear(env_level(a, 0), env_angles(d.l));
