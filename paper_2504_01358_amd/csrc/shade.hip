@@ -297,6 +297,15 @@ __global__ __launch_bounds__(256) void trace_linear_kernel(const ShadeArgs a) {
 #ifndef SSR_STEP_UNROLL
 #define SSR_STEP_UNROLL 6
 #endif
+#ifndef SSR_GUIDE_A
+#define SSR_GUIDE_A 85
+#endif
+#ifndef SSR_GUIDE_B
+#define SSR_GUIDE_B 95
+#endif
+#ifndef SSR_GUIDE_DIV
+#define SSR_GUIDE_DIV 4
+#endif
 #ifndef SSR_WAVES_PER_EU
 #define SSR_WAVES_PER_EU 5
 #endif
@@ -305,6 +314,9 @@ constexpr int kQueueLow = SSR_QUEUE_LOW;   // draw when fewer rays than this wai
 constexpr int kRefillMin = SSR_REFILL_MIN;
 constexpr int kTraceWavesPerEU = SSR_WAVES_PER_EU;
 constexpr int kStepUnroll = SSR_STEP_UNROLL;   // march iterations between idle counts
+constexpr int kGuideWhole = SSR_GUIDE_A;       // percent of tiles handed out whole,
+constexpr int kGuideHalf = SSR_GUIDE_B;        //   up to this percent in halves,
+constexpr int kGuideDiv = SSR_GUIDE_DIV;       //   the rest in this many parts
 // the queue never holds more than kQueueLow - 1 + kGenBatch * 64 rays
 constexpr int kQueueCap = 256;
 static_assert(kQueueLow - 1 + kGenBatch * 64 <= kQueueCap, "ray queue too small");
@@ -330,15 +342,40 @@ void trace_hiz_kernel(const ShadeArgs a) {
     const int n_tiles = tiles_x * ((a.H + 7) / 8);
     const int S = a.spp;
     const unsigned long long below = (1ull << lane) - 1ull;
-    auto next_tile = [&]() {
+    // work units: a tile's samples in chunks of `chunk` (a tile's 64 pixels x
+    // 16 samples is about a fifth of a millisecond of one wave's marching;
+    // smaller units let the waves finish the frame together)
+    // guided work units: whole tiles first, then the last tiles in chunks of
+    // half and a quarter of their samples, so that the waves finish the
+    // frame together (with whole tiles to the end, a wave that takes the
+    // last tile marches ~0.3 ms after others ran dry) without many more
+    // trips to the shared counter (units of one or two samples contend on it)
+    const int c1 = max(1, S / 2), c2 = max(1, S / kGuideDiv);   // chunk sizes of the tail
+    const int n1 = (n_tiles * kGuideWhole) / 100;              // whole tiles
+    const int n2 = (n_tiles * kGuideHalf) / 100;               // tiles in chunks of c1
+    const int k1 = (S + c1 - 1) / c1, k2 = (S + c2 - 1) / c2;
+    const int u1 = n1, u2 = u1 + (n2 - n1) * k1, n_units = u2 + (n_tiles - n2) * k2;
+    auto next_unit = [&]() {
         int t = 0;
         if (lane == 0) t = atomicAdd(a.tile_counter, 1);
         return __shfl(t, 0);
     };
+    int tile = 0, kk = 0, kend = 0;
+    auto set_unit = [&](int u) {
+        if (u < u1) {
+            tile = u; kk = 0; kend = S;
+        } else if (u < u2) {
+            const int v = u - u1;
+            tile = n1 + v / k1; kk = (v % k1) * c1; kend = min(kk + c1, S);
+        } else {
+            const int v = u - u2;
+            tile = n2 + v / k2; kk = (v % k2) * c2; kend = min(kk + c2, S);
+        }
+    };
     __syncthreads();
 
-    int tile = next_tile();     // tile being drawn (n_tiles or more: none left)
-    int kk = 0;                 // its next sample index
+    int unit = next_unit();     // unit being drawn (n_units or more: none left)
+    set_unit(unit);
     int qh = 0, qt = 0;         // queue head and tail (monotone; slots modulo kQueueCap)
     int nidle = 64;             // lanes without a ray
     HizRay r;
@@ -352,12 +389,12 @@ void trace_hiz_kernel(const ShadeArgs a) {
     };
     for (;;) {
         // draw more rays while the queue runs low
-        if (tile < n_tiles && qt - qh < kQueueLow) {
+        if (unit < n_units && qt - qh < kQueueLow) {
             asm volatile("" ::: "memory");
             const int i = (tile % tiles_x) * 8 + (lane & 7), j = (tile / tiles_x) * 8 + (lane >> 3);
             const bool inb = i < a.W && j < a.H;
             const int64_t q = inb ? static_cast<int64_t>(j) * a.W + i : 0;
-            const int g = min(kGenBatch, S - kk);
+            const int g = min(kGenBatch, kend - kk);
             const Pixel P = setup_pixel<DT>(a, i, j, q);
             const bool trace = inb && P.trace;
             const int fill = fill_code(a, P);
@@ -386,9 +423,9 @@ void trace_hiz_kernel(const ShadeArgs a) {
                 qt = __builtin_amdgcn_readfirstlane(qt + __popcll(m));
             }
             kk += g;
-            if (kk == S) {
-                tile = next_tile();
-                kk = 0;
+            if (kk == kend) {
+                unit = next_unit();
+                set_unit(unit);
             }
             __builtin_amdgcn_wave_barrier();
             continue;
@@ -412,12 +449,12 @@ void trace_hiz_kernel(const ShadeArgs a) {
             nidle = __popcll(__ballot(!active));
         }
         if (nidle == 64) {
-            if (tile >= n_tiles && qt == qh) break;
+            if (unit >= n_units && qt == qh) break;
             continue;
         }
         // march: one round when the queue wants more rays drawn, else until
         // enough lanes are idle to refill (all of them once nothing is queued)
-        const bool gen = tile < n_tiles && qt - qh < kQueueLow;
+        const bool gen = unit < n_units && qt - qh < kQueueLow;
         const int want = qt > qh ? min(kRefillMin, qt - qh) : 64;
         // (kStepUnroll iterations between two counts of the idle lanes: the
         // count and the loop test cost as much as a fifth of an iteration)
