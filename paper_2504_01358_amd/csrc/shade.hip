@@ -321,7 +321,9 @@ constexpr int kGuideDiv = SSR_GUIDE_DIV;       //   the rest in this many parts
 constexpr int kQueueCap = 256;
 static_assert(kQueueLow - 1 + kGenBatch * 64 <= kQueueCap, "ray queue too small");
 
-__global__ void reset_counter_kernel(int* counter) { *counter = 0; }
+// The counter starts past the units the waves take first (unit = wave index),
+// so that the waves do not all queue on it at the start.
+__global__ void reset_counter_kernel(int* counter, int first) { *counter = first; }
 
 template <int DT, int TL>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(SSR_WAVES_PER_EU, 8)))
@@ -342,9 +344,6 @@ void trace_hiz_kernel(const ShadeArgs a) {
     const int n_tiles = tiles_x * ((a.H + 7) / 8);
     const int S = a.spp;
     const unsigned long long below = (1ull << lane) - 1ull;
-    // work units: a tile's samples in chunks of `chunk` (a tile's 64 pixels x
-    // 16 samples is about a fifth of a millisecond of one wave's marching;
-    // smaller units let the waves finish the frame together)
     // guided work units: whole tiles first, then the last tiles in chunks of
     // half and a quarter of their samples, so that the waves finish the
     // frame together (with whole tiles to the end, a wave that takes the
@@ -374,7 +373,7 @@ void trace_hiz_kernel(const ShadeArgs a) {
     };
     __syncthreads();
 
-    int unit = next_unit();     // unit being drawn (n_units or more: none left)
+    int unit = blockIdx.x;      // unit being drawn (n_units or more: none left)
     set_unit(unit);
     int qh = 0, qt = 0;         // queue head and tail (monotone; slots modulo kQueueCap)
     int nidle = 64;             // lanes without a ray
@@ -537,8 +536,9 @@ hipError_t launch_trace(const ShadeArgs& args, int dtype, int march, int cu_coun
 #undef SSR_LAUNCH
         return hipGetLastError();
     }
-    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, stream, args.tile_counter);
     const dim3 grid(trace_grid(cu_count, args.W, args.H));
+    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, stream, args.tile_counter,
+                       static_cast<int>(grid.x));
 #define SSR_LAUNCH(DT, TL) \
     hipLaunchKernelGGL((trace_hiz_kernel<DT, TL>), grid, dim3(64), 0, stream, args)
     SSR_DISPATCH(dtype, tiled);
