@@ -269,13 +269,13 @@ __global__ __launch_bounds__(256) void trace_linear_kernel(const ShadeArgs a) {
 // each sample's hit code; the resolve kernel then shades each pixel from the
 // codes of its samples.
 //
-// Trace: persistent wave64s take 8 x 8 pixel tiles from a global counter.
-// The rays flow through a per-wave pool instead of being marched in
-// lockstep:
-//   * generate: every lane draws its pixel's sample k of the current tile
-//     (a few k at a time); the rays that need marching go to an LDS ring
+// Trace: persistent wave64s take work units (an 8 x 8 pixel tile's samples,
+// or a range of them near the end of the frame) from a global counter.  The
+// rays flow through a per-wave pool instead of being marched in lockstep:
+//   * generate: every lane draws its pixel's samples k of the current unit
+//     (kGenBatch at a time); the rays that need marching go to an LDS ring
 //     queue, compacted (ballot + popcount); the others get their hit code at
-//     once.  When a tile's samples are all drawn the wave takes the next tile;
+//     once.  When a unit's samples are all drawn the wave takes the next;
 //   * march: lanes take rays from the queue, any lane any ray, and a lane
 //     whose ray ends takes the next one.  Idle lanes are refilled together
 //     once kRefillMin of them wait (or the queue is shorter).
