@@ -279,10 +279,15 @@ def test_flags(ctx, flags):
     _check(_cmp(gpu, ref, f"flags{flags}"), gpu, ref, min_plain=0.9)
 
 
-@pytest.mark.parametrize("spp,max_steps", [(64, 64), (5, 1), (2, 3)])
-def test_spp_and_caps(ctx, spp, max_steps):
-    sc = scenes.make_scene("c2", width=48, height=40, spp=spp, max_steps=max_steps)
-    gpu, seen = run_gpu(ctx, sc.camera, gbuf_of(sc), sc.env, sc.params)
+@pytest.mark.parametrize("spp,max_steps,w,h,tiled", [(64, 64, 48, 40, False), (5, 1, 48, 40, False),
+                                                     (2, 3, 48, 40, False), (17, 64, 48, 40, True),
+                                                     (4096, 64, 6, 5, True)])
+def test_spp_and_caps(ctx, spp, max_steps, w, h, tiled):
+    """Sample counts from 2 to the largest accepted (4096, whose work units
+    split a tile's samples into halves and quarters), odd counts, and
+    iteration caps down to one."""
+    sc = scenes.make_scene("c2", width=w, height=h, spp=spp, max_steps=max_steps)
+    gpu, seen = run_gpu(ctx, sc.camera, gbuf_of(sc), sc.env, sc.params, tiled=tiled)
     ref = oracle_frame(sc.camera, seen, sc.env, sc.params)
     _check(_cmp(gpu, ref, f"spp{spp}-cap{max_steps}"), gpu, ref, min_plain=0.98)
 
