@@ -129,10 +129,8 @@ __device__ __forceinline__ DualRGB env_bilinear_dual(const EnvLevel& lv, const D
     const float wf = static_cast<float>(lv.w), hf = static_cast<float>(lv.h);
     TexelCoord cx, cy;
     env_texel(lv, a, cx, cy);
-    int x0 = cx.i0 % lv.w;
-    if (x0 < 0) x0 += lv.w;
-    int x1 = x0 + 1;
-    if (x1 == lv.w) x1 = 0;
+    int x0, x1;
+    env_columns(cx.i0, lv.w, x0, x1);
     const int y0 = min(max(cy.i0, 0), lv.h - 1);
     const int y1 = min(max(cy.i0 + 1, 0), lv.h - 1);
     const float4 t00 = lv.texels[y0 * lv.w + x0], t01 = lv.texels[y0 * lv.w + x1];
@@ -353,7 +351,7 @@ __global__ __launch_bounds__(256) void backward_kernel(const ShadeArgs a, const 
                     DualRGB L;
                     EnvTaps te;
                     if (code >= 0) {
-                        const float4 c1 = Texel4<DT>::load(a.radiance, code);
+                        const float3 c1 = Texel4<DT>::load3(a.radiance, code);
                         const float cv[3] = {c1.x, c1.y, c1.z};
 #pragma unroll
                         for (int c = 0; c < 3; ++c) {

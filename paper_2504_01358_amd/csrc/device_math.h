@@ -99,7 +99,8 @@ struct EnvLevel {
 };
 
 struct TexelCoord {
-    int i0;     // integer part (may be -1 or the size at the edges)
+    int i0;     // integer part (outside [0, size) near the edges and, for the
+                // other reference angle, the caller wraps or clamps it)
     float f;    // fractional part in [0, 1)
 };
 
@@ -111,16 +112,12 @@ __device__ __forceinline__ TexelCoord texel_coord(float ang, float scale_hi, flo
     const float x = offset + t;
     const float bp = x - offset;
     const float e = (offset - (x - bp)) + (t - bp);
-    float fl = floorf(x);
-    float fr = (x - fl) + (e + te);
-    if (fr < 0.0f) {
-        fr += 1.0f;
-        fl -= 1.0f;
-    } else if (fr >= 1.0f) {
-        fr -= 1.0f;
-        fl += 1.0f;
-    }
-    return TexelCoord{static_cast<int>(fl), fr};
+    const float fl = floorf(x);
+    const float fr = (x - fl) + (e + te);
+    // the error terms are far below one, so fr lies in (-1, 2) and its floor
+    // (-1, 0 or 1) moves the carry into the integer part
+    const float c = floorf(fr);
+    return TexelCoord{static_cast<int>(fl + c), fr - c};
 }
 
 struct EnvAngles {
@@ -153,8 +150,11 @@ __device__ __forceinline__ float atan2_right(float a, float b) {
 __device__ __forceinline__ EnvAngles env_angles(V3 d) {
     const bool front = d.z > 0.0f, low = d.y < 0.0f;
     const float r = __builtin_amdgcn_sqrtf(d.x * d.x + d.z * d.z);
-    return EnvAngles{front ? -atan2_right(d.x, d.z) : atan2_right(d.x, -d.z),
-                     low ? -atan2_right(r, -d.y) : atan2_right(r, d.y), front, low};
+    // (the reference is chosen through the arguments, so that a wave whose
+    // lanes look both ways evaluates each arctangent once)
+    const float phi = atan2_right(d.x, front ? d.z : -d.z);
+    const float theta = atan2_right(r, low ? -d.y : d.y);
+    return EnvAngles{front ? -phi : phi, low ? -theta : theta, front, low};
 }
 
 // 1/(2 pi) and 1/pi as float-float pairs (hi + lo to ~1e-15).
@@ -172,20 +172,31 @@ __device__ __forceinline__ void env_texel(const EnvLevel& lv, const EnvAngles& a
     cy = texel_coord(a.theta, kInvPiHi * hf, kInvPiLo * hf, a.low ? hf - 0.5f : -0.5f);
 }
 
+// Columns of the two taps of a bilinear lookup whose integer part is i0 (any
+// integer: the map wraps in azimuth) in a level of width w, a power of two,
+// so that the masks are i0 mod w and i0 + 1 mod w.
+__device__ __forceinline__ void env_columns(int i0, int w, int& x0, int& x1) {
+    x0 = i0 & (w - 1);
+    x1 = (x0 + 1) & (w - 1);
+}
+
 __device__ __forceinline__ float3 env_bilinear(const EnvLevel& lv, EnvAngles a) {
     TexelCoord cx, cy;
     env_texel(lv, a, cx, cy);
-    int x0 = cx.i0 % lv.w;
-    if (x0 < 0) x0 += lv.w;
-    int x1 = x0 + 1;
-    if (x1 == lv.w) x1 = 0;
+    int x0, x1;
+    env_columns(cx.i0, lv.w, x0, x1);
     const int y0 = min(max(cy.i0, 0), lv.h - 1);
     const int y1 = min(max(cy.i0 + 1, 0), lv.h - 1);
-    // RGB of the four taps (12 B loads from the 16 B texels)
-    const float3 t00 = *reinterpret_cast<const float3*>(lv.texels + y0 * lv.w + x0);
-    const float3 t01 = *reinterpret_cast<const float3*>(lv.texels + y0 * lv.w + x1);
-    const float3 t10 = *reinterpret_cast<const float3*>(lv.texels + y1 * lv.w + x0);
-    const float3 t11 = *reinterpret_cast<const float3*>(lv.texels + y1 * lv.w + x1);
+    // RGB of the four taps (12 B loads from the 16 B texels), at 32-bit byte
+    // offsets (a level holds at most 2^27 texels; rows and widths are below
+    // 2^24, so the 24-bit multiply is exact)
+    const char* base = reinterpret_cast<const char*>(lv.texels);
+    const unsigned r0 = __umul24(static_cast<unsigned>(y0), static_cast<unsigned>(lv.w));
+    const unsigned r1 = __umul24(static_cast<unsigned>(y1), static_cast<unsigned>(lv.w));
+    const float3 t00 = *reinterpret_cast<const float3*>(base + ((r0 + x0) << 4));
+    const float3 t01 = *reinterpret_cast<const float3*>(base + ((r0 + x1) << 4));
+    const float3 t10 = *reinterpret_cast<const float3*>(base + ((r1 + x0) << 4));
+    const float3 t11 = *reinterpret_cast<const float3*>(base + ((r1 + x1) << 4));
     const float fx = cx.f, fy = cy.f;
     const float w00 = (1.0f - fx) * (1.0f - fy), w01 = fx * (1.0f - fy);
     const float w10 = (1.0f - fx) * fy, w11 = fx * fy;

@@ -495,8 +495,8 @@ __global__ __launch_bounds__(256) void resolve_kernel(const ShadeArgs a) {
             // (a code naming no pixel of this frame contributes nothing)
             if (code >= a.W * a.H || code < SSR_HIT_SKIPPED) code = SSR_HIT_INVALID;
             if (code >= 0 || code == SSR_HIT_OFFSCREEN || code == SSR_HIT_CAP) {
-                const float4 c1 = code >= 0 ? Texel4<DT>::load(a.radiance, code)
-                                            : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                const float3 c1 = code >= 0 ? Texel4<DT>::load3(a.radiance, code)
+                                            : make_float3(0.0f, 0.0f, 0.0f);
                 const SampleDir d = sample_dir(a, P, q, s);
                 accumulate(a, P, d, code, c1, sum, cmp);
             }

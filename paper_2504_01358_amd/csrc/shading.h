@@ -20,6 +20,11 @@ struct Texel4<0> {  // float32
     __device__ static float4 load(const void* p, int64_t i) {
         return reinterpret_cast<const float4*>(p)[i];
     }
+    // the first three channels only (a 12 B load: no register is written
+    // that the caller does not read, so nothing waits on it before its use)
+    __device__ static float3 load3(const void* p, int64_t i) {
+        return *reinterpret_cast<const float3*>(reinterpret_cast<const float4*>(p) + i);
+    }
 };
 
 template <>
@@ -28,6 +33,10 @@ struct Texel4<1> {  // float16
         const ushort4 b = reinterpret_cast<const ushort4*>(p)[i];
         return make_float4(__half2float(__ushort_as_half(b.x)), __half2float(__ushort_as_half(b.y)),
                            __half2float(__ushort_as_half(b.z)), __half2float(__ushort_as_half(b.w)));
+    }
+    __device__ static float3 load3(const void* p, int64_t i) {
+        const float4 v = load(p, i);
+        return make_float3(v.x, v.y, v.z);
     }
 };
 
@@ -39,6 +48,10 @@ struct Texel4<2> {  // bfloat16: the high half of a float32
                            __uint_as_float(static_cast<uint32_t>(b.y) << 16),
                            __uint_as_float(static_cast<uint32_t>(b.z) << 16),
                            __uint_as_float(static_cast<uint32_t>(b.w) << 16));
+    }
+    __device__ static float3 load3(const void* p, int64_t i) {
+        const float4 v = load(p, i);
+        return make_float3(v.x, v.y, v.z);
     }
 };
 
@@ -188,10 +201,10 @@ __device__ __forceinline__ SampleDir sample_dir(const ShadeArgs& a, const Pixel&
 // times the radiance found (c1 at a hit pixel, loaded by the caller into
 // `c1`, the unfiltered environment otherwise), Kahan-accumulated per channel.
 __device__ __forceinline__ void accumulate(const ShadeArgs& a, const Pixel& P, const SampleDir& d,
-                                           int code, float4 c1, float* sum, float* cmp) {
+                                           int code, float3 c1, float* sum, float* cmp) {
     float3 Lr;
     if (code >= 0) {
-        Lr = make_float3(c1.x, c1.y, c1.z);
+        Lr = c1;
     } else {
         Lr = env_bilinear(env_level(a, 0), env_angles(d.l));
     }
