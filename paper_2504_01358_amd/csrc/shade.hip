@@ -103,7 +103,7 @@ struct HizRay {
     int xp, yp;           // 1 when travelling toward +x (+y), else 0
     float s_max;          // where the segment leaves the screen (at most 1)
     float iz0, diz;
-    float s, iz_in;       // current point of the segment and the ray's inverse depth there
+    float s;              // current point of the segment
     int L, ix, iy;        // level and the level-0 pixel containing the current point
     float armed;          // 1 once the ray has been in front of the depth buffer, else 0
                           // (a float: its tests compile to compares, not byte logic)
@@ -160,7 +160,6 @@ __device__ __forceinline__ bool hiz_start(const ShadeArgs& a, HizRay& r, int i, 
     r.ix = nx;
     r.iy = ny;
     r.s = se;
-    r.iz_in = fmaf(se, diz, iz0);
     return leave | (a.max_steps <= 1);
 }
 
@@ -194,8 +193,11 @@ __device__ __forceinline__ bool hiz_step(const ShadeArgs& a, const int2* lvl, Hi
     const float sec = fminf(fminf(sxc, syc), r.s_max), sep = fminf(fminf(sxp, syp), r.s_max);
     const float izc = fmaf(sec, r.diz, r.iz0), izp = fmaf(sep, r.diz, r.iz0);
     // far end (smaller inverse depth) and near end of the ray inside each cell
-    const float fc = fminf(r.iz_in, izc), nc = fmaxf(r.iz_in, izc);
-    const float fp = fminf(r.iz_in, izp), np = fmaxf(r.iz_in, izp);
+    // the ray's inverse depth at the current point (recomputed, not carried:
+    // the same FMA that gave izc or izp when the point was reached)
+    const float iz_in = fmaf(r.s, r.diz, r.iz0);
+    const float fc = fminf(iz_in, izc), nc = fmaxf(iz_in, izc);
+    const float fp = fminf(iz_in, izp), np = fmaxf(iz_in, izp);
     const bool front_c = fc > zc.x;
     const bool skip_c = front_c | (nc < zc.y);
     const bool front_p = fp > zp.x;
@@ -207,7 +209,7 @@ __device__ __forceinline__ bool hiz_step(const ShadeArgs& a, const int2* lvl, Hi
     // taken when it starts)
     const bool test = stay & at0;
     const bool was_armed = r.armed > 0.0f;
-    hit = test & (was_armed | (r.iz_in > zc.x));
+    hit = test & (was_armed | (iz_in > zc.x));
     const bool move = !hit & (!stay | at0);
     // the cell the segment moves across
     const float se = up ? sep : sec;
@@ -225,8 +227,10 @@ __device__ __forceinline__ bool hiz_step(const ShadeArgs& a, const int2* lvl, Hi
     r.ix = step ? nx : r.ix;
     r.iy = step ? ny : r.iy;
     r.s = step ? se : r.s;
-    r.iz_in = step ? (up ? izp : izc) : r.iz_in;
-    r.L = (step & up) ? Lp : ((stay & !at0) ? max(L - 2, 0) : L);
+    // (down two levels, not below 0: a saturating subtract; at level 0 a
+    // stay is the pixel test, and L stays 0 either way)
+    const int Ld = static_cast<int>(__builtin_elementwise_sub_sat(static_cast<unsigned>(L), 2u));
+    r.L = (step & up) ? Lp : (stay ? Ld : L);
     return hit | leave | (r.it >= a.max_steps);
 }
 
