@@ -21,8 +21,9 @@
 //
 // Environment derivatives first go to a per-mip-level buffer (the direct
 // term reads mip levels); the small, heavily shared top levels are summed
-// per workgroup in LDS before one atomic per texel.  A second kernel pushes
-// each level down to the level-0 texels it is the box mean of.
+// per workgroup in LDS, and the texels of the lower levels a workgroup
+// touches in an LDS hash table, before one atomic per texel.  A second
+// kernel pushes each level down to the level-0 texels it is the box mean of.
 #include "shading.h"
 
 namespace ssr {
@@ -178,11 +179,21 @@ __device__ __forceinline__ DualRGB env_bilinear_dual(const EnvLevel& lv, const D
 // ------------------------------------------------------------- the adjoint --
 
 #ifndef SSR_BW_PRIV_TEXELS
-#define SSR_BW_PRIV_TEXELS 6144
+#define SSR_BW_PRIV_TEXELS 4096
 #endif
-// top mip levels summed in LDS per workgroup (72 KB: two workgroups per CU,
-// which the register use allows anyway)
+#ifndef SSR_BW_TABLE_BITS
+#define SSR_BW_TABLE_BITS 11
+#endif
+#ifndef SSR_BW_PROBES
+#define SSR_BW_PROBES 2
+#endif
+// top mip levels summed in LDS per workgroup (48 KB), and a table of
+// 2^SSR_BW_TABLE_BITS slots (16 KB) that sums the other texels the
+// workgroup touches before they go out as global atomics: 64 KB, two
+// workgroups per CU, which the register use allows anyway
 constexpr int kPrivTexels = SSR_BW_PRIV_TEXELS;
+constexpr int kTableBits = SSR_BW_TABLE_BITS;
+constexpr int kTableSlots = 1 << kTableBits;
 
 struct BackArgs {
     const float* g_out;       // [H][W][3]
@@ -198,9 +209,40 @@ struct BackArgs {
     int64_t texels;           // texels of one copy
 };
 
-// The workgroup's sums of the top mip levels (file scope, so that the
+// The workgroup's sums of the top mip levels, and the table: slot k holds
+// the texel lds_tag[k] (-1: free) and its RGB sum (file scope, so that the
 // compiler sees LDS and issues LDS atomics).
 __shared__ float lds_env[3 * kPrivTexels];
+__shared__ int lds_tag[kTableSlots];
+__shared__ float lds_tab[3 * kTableSlots];
+
+// Add (r, g, bl) to texel `texel` of the lower levels: into the table slot
+// the texel owns, or claims while it is free (two probes); else (both slots
+// owned by other texels) straight to the global sums.  Device-scope float
+// atomics are performed beyond the per-XCD L2 caches, so each one saved
+// here is a round trip over the fabric.
+__device__ __forceinline__ void add_lower(const BackArgs& b, int texel, float r, float g, float bl) {
+    const unsigned h = (static_cast<unsigned>(texel) * 2654435761u) >> (32 - kTableBits);
+#pragma unroll
+    for (int p = 0; p < SSR_BW_PROBES; ++p) {
+        const unsigned slot = (h + p) & (kTableSlots - 1);
+        int cur = lds_tag[slot];
+        if (cur == -1) {
+            const int old = atomicCAS(&lds_tag[slot], -1, texel);
+            cur = old == -1 ? texel : old;
+        }
+        if (cur == texel) {
+            atomicAdd(&lds_tab[3 * slot + 0], r);
+            atomicAdd(&lds_tab[3 * slot + 1], g);
+            atomicAdd(&lds_tab[3 * slot + 2], bl);
+            return;
+        }
+    }
+    float* q = reinterpret_cast<float*>(b.g_mips + texel);
+    atomicAdd(q + 0, r);
+    atomicAdd(q + 1, g);
+    atomicAdd(q + 2, bl);
+}
 
 __device__ __forceinline__ void add_env(const BackArgs& b, int level_offset, int level,
                                         const EnvTaps& t, const float coef[3]) {
@@ -215,10 +257,7 @@ __device__ __forceinline__ void add_env(const BackArgs& b, int level_offset, int
             atomicAdd(&lds_env[at + 1], w * coef[1]);
             atomicAdd(&lds_env[at + 2], w * coef[2]);
         } else {
-            float* p = reinterpret_cast<float*>(b.g_mips + texel);
-            atomicAdd(p + 0, w * coef[0]);
-            atomicAdd(p + 1, w * coef[1]);
-            atomicAdd(p + 2, w * coef[2]);
+            add_lower(b, texel, w * coef[0], w * coef[1], w * coef[2]);
         }
     }
 }
@@ -226,6 +265,12 @@ __device__ __forceinline__ void add_env(const BackArgs& b, int level_offset, int
 template <int DT>
 __global__ __launch_bounds__(256) void backward_kernel(const ShadeArgs a, const BackArgs b0) {
     for (int k = threadIdx.x; k < 3 * b0.priv_texels; k += blockDim.x) lds_env[k] = 0.0f;
+    for (int k = threadIdx.x; k < kTableSlots; k += blockDim.x) {
+        lds_tag[k] = -1;
+        lds_tab[3 * k + 0] = 0.0f;
+        lds_tab[3 * k + 1] = 0.0f;
+        lds_tab[3 * k + 2] = 0.0f;
+    }
     // workgroups spread their global atomics over `replicas` copies of the
     // per-texel sums, so that many pixels reading the same texels do not
     // all queue on one address
@@ -399,7 +444,8 @@ __global__ __launch_bounds__(256) void backward_kernel(const ShadeArgs a, const 
             if (b.g_am) reinterpret_cast<float4*>(b.g_am)[q] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         }
     }
-    // this workgroup's sums of the top levels, one atomic per texel
+    // this workgroup's sums of the top levels and of the table's texels, one
+    // atomic per texel and channel
     __syncthreads();
     for (int k = threadIdx.x; k < b.priv_texels; k += blockDim.x) {
         const float* p = lds_env + 3 * k;
@@ -409,6 +455,15 @@ __global__ __launch_bounds__(256) void backward_kernel(const ShadeArgs a, const 
             atomicAdd(dst + 1, p[1]);
             atomicAdd(dst + 2, p[2]);
         }
+    }
+    for (int k = threadIdx.x; k < kTableSlots; k += blockDim.x) {
+        const int texel = lds_tag[k];
+        if (texel < 0) continue;
+        const float* p = lds_tab + 3 * k;
+        float* dst = reinterpret_cast<float*>(b.g_mips + texel);
+        atomicAdd(dst + 0, p[0]);
+        atomicAdd(dst + 1, p[1]);
+        atomicAdd(dst + 2, p[2]);
     }
 }
 
