@@ -1,6 +1,11 @@
 """The adjoint on the GPU (hit codes held fixed): against the FP64 oracle's
 reference derivatives, against finite differences of the GPU's own forward
-on the 800x800 differentiation workload, and through torch.autograd."""
+on the 800x800 differentiation workload, and through torch.autograd.
+
+The hit codes both sides replay are inputs of the estimator whose
+derivatives are taken; they are drawn by the oracle's own march (the GPU's
+march has its own parity tests), so no expected value depends on a GPU
+result."""
 
 import numpy as np
 import pytest
@@ -48,6 +53,19 @@ def _gbuf(sc):
                 radiance=sc.radiance)
 
 
+def _oracle_hits(sc, dev, pix=None, base=None):
+    """Hit codes [H][W][S] int32 on `dev` from the oracle's march: the whole
+    frame, or only the pixels `pix` written into a copy of `base` (the
+    derivatives of a pixel depend on its own codes alone)."""
+    if pix is None:
+        h = oracle.shade_frame(sc.camera, _gbuf(sc), sc.env, sc.params)["hits"]
+        return torch.from_numpy(np.ascontiguousarray(h.astype(np.int32))).to(dev)
+    r = oracle.shade_pixels(sc.camera, _gbuf(sc), sc.env, sc.params, pix)
+    h = base.clone().reshape(-1, sc.params["spp"])
+    h[torch.from_numpy(np.asarray(pix)).to(dev)] = torch.from_numpy(r["hits"].astype(np.int32)).to(dev)
+    return h.reshape(base.shape)
+
+
 def _backward(ctx, sc, t, hits, g_out, env=True, rad=True):
     dev = t["depth"].device
     H, W = sc.height, sc.width
@@ -88,8 +106,7 @@ def test_pixel_gradients_match_oracle(ctx, flags):
     sc.params["flags"] = flags
     dev = torch.device("cuda", 0)
     t = _up(sc, dev)
-    hits = ctx.trace(sc.camera, t["depth"], t["normal_rough"], t["albedo_metal"], t["radiance"],
-                     sc.params)
+    hits = _oracle_hits(sc, dev)
     g_out = np.random.default_rng(7).normal(size=(32, 48, 3))
     got = _backward(ctx, sc, t, hits, g_out, env=False, rad=False)
     h = hits.cpu().numpy().reshape(-1, 4)
@@ -106,8 +123,7 @@ def test_env_and_radiance_gradients_match_oracle(ctx):
     sc.env = np.ascontiguousarray(sc.env[::32, ::32])          # 8 x 16 map: every texel checked
     dev = torch.device("cuda", 0)
     t = _up(sc, dev)
-    hits = ctx.trace(sc.camera, t["depth"], t["normal_rough"], t["albedo_metal"], t["radiance"],
-                     sc.params)
+    hits = _oracle_hits(sc, dev)
     g_out = np.random.default_rng(8).normal(size=(20, 32, 3))
     got = _backward(ctx, sc, t, hits, g_out)
     h = hits.cpu().numpy()
@@ -119,6 +135,32 @@ def test_env_and_radiance_gradients_match_oracle(ctx):
     _agree(got["g_rad"][..., :3].reshape(-1, 1), want_rad.reshape(-1, 1), "radiance grads",
            rel=1e-4, frac=1.0)
     assert np.all(got["g_rad"][..., 3] == 0)
+
+
+def test_env_gradients_of_a_full_size_map(ctx):
+    """A 128 x 256 map (the differentiation workload's size): the two largest
+    levels exceed the LDS copy of the top levels, so their derivatives go
+    through the workgroup hash table and the replicas, and every level is
+    pushed down.  48 texels against the oracle (exact by linearity): half at
+    random, half those with the largest derivatives (the level-0 lookups of
+    the misses), one channel each."""
+    sc = scenes.make_scene("c2", seed=64, width=40, height=24, spp=4)
+    sc.env = np.ascontiguousarray(sc.env[::2, ::2])
+    dev = torch.device("cuda", 0)
+    t = _up(sc, dev)
+    hits = _oracle_hits(sc, dev)
+    g_out = np.random.default_rng(10).normal(size=(24, 40, 3))
+    got = _backward(ctx, sc, t, hits, g_out, rad=False)
+    he, we = sc.env.shape[:2]
+    assert (he, we) == (128, 256)
+    rng = np.random.default_rng(11)
+    flat = np.abs(got["g_env"]).reshape(-1)
+    top = np.argsort(flat)[-24:]
+    pick = np.concatenate([rng.choice(flat.size, 24, replace=False), top])
+    tex = [(int(k // (3 * we)), int(k // 3 % we), int(k % 3)) for k in pick]
+    want = ograd.env_grads(sc.camera, _gbuf(sc), sc.env, sc.params, hits.cpu().numpy(), g_out, tex)
+    gpu = np.array([got["g_env"][y, x, c] for (y, x, c) in tex])
+    _agree(gpu.reshape(-1, 1), want.reshape(-1, 1), "env grads 128x256", rel=1e-4, frac=1.0)
 
 
 def test_finite_differences_on_the_differentiation_workload(ctx):
@@ -136,13 +178,16 @@ def test_finite_differences_on_the_differentiation_workload(ctx):
     sc = _interior(scenes.make_scene("c4"), 2, tilt=0.1)
     dev = torch.device("cuda", 0)
     t = _up(sc, dev)
-    hits = ctx.trace(sc.camera, t["depth"], t["normal_rough"], t["albedo_metal"], t["radiance"],
-                     sc.params)
     rng = np.random.default_rng(9)
     g_out = rng.normal(size=(800, 800, 3))
-    got = _backward(ctx, sc, t, hits, g_out, env=False, rad=False)
     fg = np.nonzero(np.isfinite(sc.depth.reshape(-1)))[0]
     pix = rng.choice(fg, 64, replace=False)
+    # the checked pixels replay the oracle's codes; the rest of the frame
+    # (which none of the checked values depends on) the GPU's
+    hits = ctx.trace(sc.camera, t["depth"], t["normal_rough"], t["albedo_metal"], t["radiance"],
+                     sc.params)
+    hits = _oracle_hits(sc, dev, pix, hits)
+    got = _backward(ctx, sc, t, hits, g_out, env=False, rad=False)
     pix_t = torch.from_numpy(pix).to(dev)
     g_t = torch.from_numpy(g_out.astype(np.float32)).to(dev).reshape(-1, 3)
     gpu = np.concatenate([got["g_nr"].reshape(-1, 4)[pix], got["g_am"].reshape(-1, 4)[pix]], axis=1)
