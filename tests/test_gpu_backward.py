@@ -54,16 +54,17 @@ def _gbuf(sc):
 
 
 def _oracle_hits(sc, dev, pix=None, base=None):
-    """Hit codes [H][W][S] int32 on `dev` from the oracle's march: the whole
-    frame, or only the pixels `pix` written into a copy of `base` (the
-    derivatives of a pixel depend on its own codes alone)."""
+    """Hit codes from the oracle's march: (codes on `dev` for the GPU, the
+    same codes as a host array for the oracle).  The whole frame [H][W][S],
+    or only the pixels `pix` ([n][S] on the host) written into a copy of
+    `base` (the derivatives of a pixel depend on its own codes alone)."""
     if pix is None:
-        h = oracle.shade_frame(sc.camera, _gbuf(sc), sc.env, sc.params)["hits"]
-        return torch.from_numpy(np.ascontiguousarray(h.astype(np.int32))).to(dev)
-    r = oracle.shade_pixels(sc.camera, _gbuf(sc), sc.env, sc.params, pix)
-    h = base.clone().reshape(-1, sc.params["spp"])
-    h[torch.from_numpy(np.asarray(pix)).to(dev)] = torch.from_numpy(r["hits"].astype(np.int32)).to(dev)
-    return h.reshape(base.shape)
+        h = oracle.shade_frame(sc.camera, _gbuf(sc), sc.env, sc.params)["hits"].astype(np.int32)
+        return torch.from_numpy(np.ascontiguousarray(h)).to(dev), h
+    h = oracle.shade_pixels(sc.camera, _gbuf(sc), sc.env, sc.params, pix)["hits"].astype(np.int32)
+    d = base.clone().reshape(-1, sc.params["spp"])
+    d[torch.from_numpy(np.asarray(pix)).to(dev)] = torch.from_numpy(h).to(dev)
+    return d.reshape(base.shape), h
 
 
 def _backward(ctx, sc, t, hits, g_out, env=True, rad=True):
@@ -106,10 +107,10 @@ def test_pixel_gradients_match_oracle(ctx, flags):
     sc.params["flags"] = flags
     dev = torch.device("cuda", 0)
     t = _up(sc, dev)
-    hits = _oracle_hits(sc, dev)
+    hits, h = _oracle_hits(sc, dev)
     g_out = np.random.default_rng(7).normal(size=(32, 48, 3))
     got = _backward(ctx, sc, t, hits, g_out, env=False, rad=False)
-    h = hits.cpu().numpy().reshape(-1, 4)
+    h = h.reshape(-1, 4)
     pix = np.arange(48 * 32)
     want = ograd.pixel_grads(sc.camera, _gbuf(sc), sc.env, sc.params, pix, h,
                              g_out.reshape(-1, 3))
@@ -123,10 +124,9 @@ def test_env_and_radiance_gradients_match_oracle(ctx):
     sc.env = np.ascontiguousarray(sc.env[::32, ::32])          # 8 x 16 map: every texel checked
     dev = torch.device("cuda", 0)
     t = _up(sc, dev)
-    hits = _oracle_hits(sc, dev)
+    hits, h = _oracle_hits(sc, dev)
     g_out = np.random.default_rng(8).normal(size=(20, 32, 3))
     got = _backward(ctx, sc, t, hits, g_out)
-    h = hits.cpu().numpy()
     he, we = sc.env.shape[:2]
     tex = [(y, x, c) for y in range(he) for x in range(we) for c in range(3)]
     want_env = ograd.env_grads(sc.camera, _gbuf(sc), sc.env, sc.params, h, g_out, tex)
@@ -148,7 +148,7 @@ def test_env_gradients_of_a_full_size_map(ctx):
     sc.env = np.ascontiguousarray(sc.env[::2, ::2])
     dev = torch.device("cuda", 0)
     t = _up(sc, dev)
-    hits = _oracle_hits(sc, dev)
+    hits, h = _oracle_hits(sc, dev)
     g_out = np.random.default_rng(10).normal(size=(24, 40, 3))
     got = _backward(ctx, sc, t, hits, g_out, rad=False)
     he, we = sc.env.shape[:2]
@@ -158,7 +158,7 @@ def test_env_gradients_of_a_full_size_map(ctx):
     top = np.argsort(flat)[-24:]
     pick = np.concatenate([rng.choice(flat.size, 24, replace=False), top])
     tex = [(int(k // (3 * we)), int(k // 3 % we), int(k % 3)) for k in pick]
-    want = ograd.env_grads(sc.camera, _gbuf(sc), sc.env, sc.params, hits.cpu().numpy(), g_out, tex)
+    want = ograd.env_grads(sc.camera, _gbuf(sc), sc.env, sc.params, h, g_out, tex)
     gpu = np.array([got["g_env"][y, x, c] for (y, x, c) in tex])
     _agree(gpu.reshape(-1, 1), want.reshape(-1, 1), "env grads 128x256", rel=1e-4, frac=1.0)
 
@@ -186,7 +186,7 @@ def test_finite_differences_on_the_differentiation_workload(ctx):
     # (which none of the checked values depends on) the GPU's
     hits = ctx.trace(sc.camera, t["depth"], t["normal_rough"], t["albedo_metal"], t["radiance"],
                      sc.params)
-    hits = _oracle_hits(sc, dev, pix, hits)
+    hits, h = _oracle_hits(sc, dev, pix, hits)
     got = _backward(ctx, sc, t, hits, g_out, env=False, rad=False)
     pix_t = torch.from_numpy(pix).to(dev)
     g_t = torch.from_numpy(g_out.astype(np.float32)).to(dev).reshape(-1, 3)
@@ -215,7 +215,6 @@ def test_finite_differences_on_the_differentiation_workload(ctx):
         l1 = float(np.abs(gpu[:, ch]).sum())
         print(f"[c4 directional ch={ch}] fd {d:.6g} adjoint {a:.6g} l1 {l1:.6g}", flush=True)
         assert abs(d - a) <= (0.05 if ch == 3 else 0.02) * l1, (ch, d, a, l1)
-    h = hits.cpu().numpy().reshape(-1, sc.params["spp"])[pix]
     want = ograd.pixel_grads(sc.camera, _gbuf(sc), sc.env, sc.params, pix, h,
                              g_out.reshape(-1, 3)[pix])
     _agree(gpu, want, "c4 oracle", rel=2e-3, frac=60 / 64)
