@@ -247,6 +247,37 @@ def time_gpu(ctx, scene, dtype, steps, warmup, dev, mips):
                 hiz_ms=float(np.mean(hiz_ms)), **work)
 
 
+def time_linear(ctx, scene, dev, mips, reps=20):
+    """The same frame with the march of Algorithm 1 (the paper's linear
+    march: 32 world-space steps of 0.125 up to a ray length of 4, the
+    parameters of the small configuration) instead of the hierarchical one."""
+    import torch
+
+    from paper_2504_01358_amd import ssr
+    t = upload(scene, "f32", dev)
+    H, W, S = scene.height, scene.width, scene.params["spp"]
+    prm = dict(scene.params, march=0, max_steps=32, step_len=0.125, max_dist=4.0)
+    out = torch.empty((H, W, 3), dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    cam, p = ssr.make_camera(scene.camera), ssr.make_params(prm)
+
+    def step():
+        ctx.shade(cam, t["depth"], t["normal_rough"], t["albedo_metal"], t["radiance"], t["env"], p,
+                  env_mips=mips, out=out, stream=stream)
+    for _ in range(3):
+        step()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    return {"ms_per_step": ms, "value": H * W * S / (ms * 1e-3) / 1e6, "unit": "Mrays/s",
+            "march": "linear (Algorithm 1): 32 steps of 0.125, ray length <= 4, thickness 0.05"}
+
+
 def _oracle_rows(args):
     cfg, rows = args
     os.environ["OMP_NUM_THREADS"] = "1"
@@ -570,6 +601,9 @@ def main():
             line[dt] = {"value": rays / (res[dt]["ms_per_step"] * 1e-3) / 1e6,
                         "ms_per_step": res[dt]["ms_per_step"], "trace_ms": res[dt]["trace_ms"],
                         "resolve_ms": res[dt]["resolve_ms"]}
+    line["linear"] = time_linear(ctx, scene, dev, mips)
+    print(f"bench: linear march {line['linear']['ms_per_step']:.3f} ms/frame", file=sys.stderr,
+          flush=True)
     if not args.no_first_pass:
         line["first_pass"] = time_first_pass(ctx, scene, dev)
         fp = line["first_pass"]["first_pass_f32"]
