@@ -26,27 +26,49 @@ struct MarchResult {
 };
 
 // Fixed world-space steps (Appendix D, Algorithm 1, with the documented hit
-// rule).  V0 view-space origin, Dv view-space direction.
+// rule).  V0 view-space origin, Dv view-space direction.  The sample points
+// are known in advance, so the depths of kLinearAhead of them are loaded
+// together (at clamped, in-bounds pixels) and then tested in order: the
+// march waits for one group of gathers instead of one gather per step.
+#ifndef SSR_LINEAR_AHEAD
+#define SSR_LINEAR_AHEAD 4
+#endif
+constexpr int kLinearAhead = SSR_LINEAR_AHEAD;
+
 __device__ __forceinline__ MarchResult march_linear(const ShadeArgs& a, int i, int j, V3 V0, V3 Dv) {
     bool armed = false;
-    for (int k = 1; k <= a.linear_samples; ++k) {
-        const float t = static_cast<float>(k) * a.step_len;
-        const float X = V0.x + t * Dv.x, Y = V0.y + t * Dv.y, Z = V0.z + t * Dv.z;
-        if (!(Z > a.z_near)) return MarchResult{SSR_HIT_OFFSCREEN, k};
-        const float iz = 1.0f / Z;
-        const float px = a.cx + a.fx * X * iz;
-        const float py = a.cy - a.fy * Y * iz;
-        if (!(px >= 0.0f && px < static_cast<float>(a.W) && py >= 0.0f &&
-              py < static_cast<float>(a.H)))
-            return MarchResult{SSR_HIT_OFFSCREEN, k};
-        const int ix = min(static_cast<int>(floorf(px)), a.W - 1);
-        const int iy = min(static_cast<int>(floorf(py)), a.H - 1);
-        if (ix == i && iy == j) continue;
-        const float dz = Z - a.depth[static_cast<int64_t>(iy) * a.W + ix];
-        if (armed && dz >= 0.0f && dz <= a.thickness) return MarchResult{iy * a.W + ix, k};
-        if (dz < 0.0f) armed = true;
+    const int K = a.linear_samples;
+    for (int k0 = 1; k0 <= K; k0 += kLinearAhead) {
+        float Z[kLinearAhead], D[kLinearAhead];
+        int ix[kLinearAhead], iy[kLinearAhead];
+        bool on[kLinearAhead];
+#pragma unroll
+        for (int u = 0; u < kLinearAhead; ++u) {
+            const float t = static_cast<float>(k0 + u) * a.step_len;
+            const float X = V0.x + t * Dv.x, Y = V0.y + t * Dv.y;
+            Z[u] = V0.z + t * Dv.z;
+            const float iz = 1.0f / Z[u];
+            const float px = a.cx + a.fx * X * iz;
+            const float py = a.cy - a.fy * Y * iz;
+            on[u] = Z[u] > a.z_near && px >= 0.0f && px < static_cast<float>(a.W) && py >= 0.0f &&
+                    py < static_cast<float>(a.H);
+            // (off the screen the load reads pixel (0, 0) and is not used)
+            ix[u] = min(static_cast<int>(floorf(on[u] ? px : 0.0f)), a.W - 1);
+            iy[u] = min(static_cast<int>(floorf(on[u] ? py : 0.0f)), a.H - 1);
+            D[u] = a.depth[static_cast<int64_t>(iy[u]) * a.W + ix[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < kLinearAhead; ++u) {
+            const int k = k0 + u;
+            if (k > K) break;
+            if (!on[u]) return MarchResult{SSR_HIT_OFFSCREEN, k};
+            if (ix[u] == i && iy[u] == j) continue;
+            const float dz = Z[u] - D[u];
+            if (armed && dz >= 0.0f && dz <= a.thickness) return MarchResult{iy[u] * a.W + ix[u], k};
+            if (dz < 0.0f) armed = true;
+        }
     }
-    return MarchResult{SSR_HIT_CAP, a.linear_samples};
+    return MarchResult{SSR_HIT_CAP, K};
 }
 
 // ------------------------------------------------------ hierarchical march --
