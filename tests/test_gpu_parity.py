@@ -292,6 +292,25 @@ def test_spp_and_caps(ctx, spp, max_steps, w, h, tiled):
     _check(_cmp(gpu, ref, f"spp{spp}-cap{max_steps}"), gpu, ref, min_plain=0.98)
 
 
+@pytest.mark.parametrize("max_steps,max_dist", [(1, 4.0), (3, 4.0), (5, 4.0), (30, 4.0),
+                                                (32, 0.7), (64, 10.0)])
+def test_linear_step_counts(ctx, max_steps, max_dist):
+    """The linear march's step count K = min(max_steps, floor(max_dist / step))
+    at 1, 3, 5, 30, 5 (bound by the ray length) and 64: the kernel tests its
+    sample points in groups of four, so K off a multiple of four ends a ray
+    inside a group.  Hit codes and step counts against the oracle."""
+    sc = scenes.make_scene("c2", width=48, height=40, spp=4, march="linear",
+                           max_steps=max_steps, max_dist=max_dist)
+    gpu, seen = run_gpu(ctx, sc.camera, gbuf_of(sc), sc.env, sc.params)
+    ref = oracle_frame(sc.camera, seen, sc.env, sc.params)
+    _check(_cmp(gpu, ref, f"linear-K{max_steps}-{max_dist}"), gpu, ref, min_plain=0.98)
+    K = min(max_steps, int(np.floor(max_dist / sc.params["step_len"])))
+    assert gpu["steps"].max() <= K
+    # every ray that ran out of steps took exactly K
+    from paper_2504_01358_amd import ssr
+    assert (gpu["steps"][gpu["hits"] == ssr.HIT_CAP] == K).all()
+
+
 def test_backfacing_and_unnormalised_normals(ctx):
     sc = scenes.make_scene("c2", width=64, height=48, spp=2)
     g = gbuf_of(sc)
