@@ -86,11 +86,13 @@ hipError_t launch_env_mips(const float* rgb, const EnvLayout& lay, float4* mips,
 
 // ------------------------------------------------------------ Hi-Z pyramid --
 //
-// Pass 1: one 256-thread workgroup per 64 x 64 depth tile writes levels 0..6
-// of that tile.  Each thread reduces a 4 x 4 pixel block to its
-// (1/D, 1/(D + thickness)) level-0 pairs, two level-1 rows and one level-2
-// texel in registers; the 16 x 16 level-2 texels go through LDS for levels
-// 3..6.  A texel at level L is the (max, min) of those pairs over the
+// Pass 1: one 256-thread workgroup per 32 x 32 depth tile writes levels 0..5
+// of that tile.  Each thread reduces a 2 x 2 pixel block to its
+// (1/D, 1/(D + thickness)) level-0 pairs and one level-1 texel in
+// registers; the 16 x 16 level-1 texels go through LDS for levels 2..5.
+// (Small blocks give eight waves per SIMD at 1080p, enough to cover the
+// latency of the depth loads; 4 x 4 blocks ran at two and took 25 % longer.)
+// A texel at level L is the (max, min) of those pairs over the
 // 2^L x 2^L pixel block it covers, clipped to the image (pixels outside
 // count as -inf for the max and +inf for the min), which equals the
 // ceil-halving recursion.  Texels that do not exist at their level
@@ -98,13 +100,13 @@ hipError_t launch_env_mips(const float* rgb, const EnvLayout& lay, float4* mips,
 // rounded and rounding is monotone, so a texel equals the rounded inverse of
 // the block's minimum depth and of its maximum (depth + thickness) exactly.
 //
-// Pass 2: the levels above 6.  When level 6 fits in LDS, one workgroup does
+// Pass 2: the levels above 5.  When level 5 fits in LDS, one workgroup does
 // them all there; otherwise one launch per level from global memory.
 //
 // Texels are stored as (own pair, parent's pair), see put_level.
 
-constexpr int kTile = 64;
-constexpr int kTileLevels = 6;
+constexpr int kTile = 32;
+constexpr int kTileLevels = 5;
 
 // (max inverse depth, min inverse depth) of two texels
 __device__ __forceinline__ float2 mm(float2 a, float2 b) {
@@ -150,13 +152,13 @@ __global__ __launch_bounds__(256) void hiz_tile_kernel(const float* __restrict__
     const int W = lay.w[0], H = lay.h[0];
     const int top = lay.levels - 1;
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-    const int x0 = blockIdx.x * kTile + tx * 4;
-    const int y0 = blockIdx.y * kTile + ty * 4;
-    float2 p[4][4];
+    const int x0 = blockIdx.x * kTile + tx * 2;
+    const int y0 = blockIdx.y * kTile + ty * 2;
+    float2 p[2][2];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
+    for (int r = 0; r < 2; ++r) {
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
+        for (int c = 0; c < 2; ++c) {
             const int x = x0 + c, y = y0 + r;
             const bool in = x < W && y < H;
             const float D = in ? depth[static_cast<int64_t>(y) * W + x] : 1.0f;
@@ -164,53 +166,32 @@ __global__ __launch_bounds__(256) void hiz_tile_kernel(const float* __restrict__
                          : make_float2(-INFINITY, INFINITY);
         }
     }
-    // level 1: 2 x 2 texels per thread
-    float2 m1[2][2];
+    const float2 m1 = mm(mm(p[0][0], p[0][1]), mm(p[1][0], p[1][1]));
+    // level 0 with its parents (level 1) from registers
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int r = 0; r < 2; ++r)
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
-            m1[b][a] = mm(mm(p[2 * b][2 * a], p[2 * b][2 * a + 1]),
-                          mm(p[2 * b + 1][2 * a], p[2 * b + 1][2 * a + 1]));
-    const float2 m2 = mm(mm(m1[0][0], m1[0][1]), mm(m1[1][0], m1[1][1]));
-    // levels 0 and 1 with their parents (levels 1 and 2) from registers
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
+        for (int c = 0; c < 2; ++c) {
             const int x = x0 + c, y = y0 + r;
             if (x < W && y < H) {
-                const float2 par = top >= 1 ? m1[r >> 1][c >> 1] : p[r][c];
+                const float2 par = top >= 1 ? m1 : p[r][c];
                 pyr[static_cast<int64_t>(y) * W + x] = make_float4(p[r][c].x, p[r][c].y, par.x, par.y);
             }
         }
     if (tile_levels < 1) return;
     {
+        // level 1: its parent comes from the LDS pass below (or it is the top)
         const int lx = x0 / 2, ly = y0 / 2;
-#pragma unroll
-        for (int b = 0; b < 2; ++b)
-#pragma unroll
-            for (int a = 0; a < 2; ++a)
-                if (lx + a < lay.w[1] && ly + b < lay.h[1]) {
-                    const float2 par = top >= 2 ? m2 : m1[b][a];
-                    pyr[lay.offset[1] + (ly + b) * lay.w[1] + lx + a] =
-                        make_float4(m1[b][a].x, m1[b][a].y, par.x, par.y);
-                }
-    }
-    if (tile_levels < 2) return;
-    {
-        // level 2: its parent comes from the LDS pass below (or it is the top)
-        const int lx = x0 / 4, ly = y0 / 4;
-        if (lx < lay.w[2] && ly < lay.h[2]) {
-            const int64_t at = lay.offset[2] + ly * lay.w[2] + lx;
-            put(pyr, at, m2);
-            if (top == 2) put_parent(pyr, at, m2);
+        if (lx < lay.w[1] && ly < lay.h[1]) {
+            const int64_t at = lay.offset[1] + ly * lay.w[1] + lx;
+            put(pyr, at, m1);
+            if (top == 1) put_parent(pyr, at, m1);
         }
     }
-    lds[0][ty * 16 + tx] = m2;
+    lds[0][ty * 16 + tx] = m1;
     int n = 16;  // current level's tile width in texels
     int cur = 0;
-    for (int L = 3; L <= tile_levels; ++L) {
+    for (int L = 2; L <= tile_levels; ++L) {
         __syncthreads();
         const int m = n / 2;
         if (static_cast<int>(threadIdx.x) < m * m) {
