@@ -524,7 +524,12 @@ __global__ __launch_bounds__(256) void resolve_kernel(const ShadeArgs a) {
                 const float3 c1 = code >= 0 ? Texel4<DT>::load3(a.radiance, code)
                                             : make_float3(0.0f, 0.0f, 0.0f);
                 const SampleDir d = sample_dir(a, P, q, s);
-                accumulate(a, P, d, code, c1, sum, cmp);
+                // a miss's environment lookup goes to registers of its own and
+                // the choice comes after it, so the lookup does not wait for
+                // the radiance loads of the wave's hit lanes
+                float3 e = make_float3(0.0f, 0.0f, 0.0f);
+                if (code < 0) e = env_bilinear(env_level(a, 0), env_angles(d.l));
+                accumulate(a, P, d, code >= 0 ? c1 : e, sum, cmp);
             }
         }
     }

@@ -198,16 +198,10 @@ __device__ __forceinline__ SampleDir sample_dir(const ShadeArgs& a, const Pixel&
 }
 
 // Weight F(wo.h) G1(n.l) (visible normals; NDF sampling: the weight above)
-// times the radiance found (c1 at a hit pixel, loaded by the caller into
-// `c1`, the unfiltered environment otherwise), Kahan-accumulated per channel.
+// times the radiance Lr found along the sample (c1 at a hit pixel, the
+// unfiltered environment otherwise), Kahan-accumulated per channel.
 __device__ __forceinline__ void accumulate(const ShadeArgs& a, const Pixel& P, const SampleDir& d,
-                                           int code, float3 c1, float* sum, float* cmp) {
-    float3 Lr;
-    if (code >= 0) {
-        Lr = c1;
-    } else {
-        Lr = env_bilinear(env_level(a, 0), env_angles(d.l));
-    }
+                                           float3 Lr, float* sum, float* cmp) {
     const float fc = 1.0f - d.cos_oh;
     const float fc2 = fc * fc;
     const float fr = fc2 * fc2 * fc;
