@@ -14,7 +14,9 @@
  * the specular integral (Sec. 3.3, the estimator over N_s sampled rays): each
  * sample draws a GGX visible normal, reflects the view direction about it,
  * marches the ray in screen space against the depth buffer (Sec. 3.3 and
- * Appendix D, Algorithm 1, or a hierarchical-Z version of the same test), and
+ * Appendix D, Algorithm 1, in fixed steps; or this library's own
+ * hierarchical traversal of the same hit test over a min-max depth pyramid,
+ * which the paper does not describe), and
  * weights the radiance found at the hit (c1 of the hit pixel; the environment
  * when the ray leaves the screen) by F(wo.h) G1(n.l) (Appendix B with
  * alpha = rho).
@@ -68,9 +70,13 @@ typedef enum {
 typedef enum { SSR_F32 = 0, SSR_F16 = 1, SSR_BF16 = 2 } ssr_dtype;
 
 /* March modes.  LINEAR: fixed world-space steps (Appendix D, Algorithm 1).
- * HIZ: exact first hit on the depth heightfield, traversed over a min-max
- * depth pyramid with at most max_steps iterations (skip a cell the ray passes
- * wholly in front of or wholly behind, descend, or test a pixel: one each). */
+ * HIZ: exact first hit on the depth heightfield under the same hit test,
+ * traversed over a min-max depth pyramid with at most max_steps iterations
+ * (skip a cell the ray passes wholly in front of or wholly behind, descend,
+ * or test a pixel: one each).  The paper marches in fixed steps only (Sec. 3.3
+ * cites a DDA tracer); the hierarchical traversal is this library's design,
+ * and with the cap lifted it returns the first crossing a pixel-by-pixel scan
+ * of the segment finds. */
 enum { SSR_MARCH_LINEAR = 0, SSR_MARCH_HIZ = 1 };
 
 /* Flags: drop the direct diffuse term, or the Monte-Carlo specular term;
@@ -177,7 +183,8 @@ int ssr_shade(ssr_ctx* ctx, const ssr_camera* cam, const ssr_gbuffer* gbuf,
               const ssr_env* env, const ssr_params* params, float* out_rgb,
               int32_t* out_hits, int32_t* out_steps, void* stream);
 
-/* The march half of ssr_shade (Sec. 3.3 sampling, Appendix D march): write
+/* The march half of ssr_shade (Sec. 3.3 sampling; the march of Appendix D,
+ * Algorithm 1, or the library's hierarchical march, per params->march): write
  * every sample's hit code to out_hits ([H][W][spp] int32, or tile-major with
  * SSR_CODES_TILED; required) and,
  * unless NULL, its iteration count to out_steps.  Reads depth and the
@@ -248,8 +255,9 @@ int ssr_env_build_mips(const float* rgb, int32_t width, int32_t height, float* m
 int64_t ssr_hiz_floats(int32_t width, int32_t height);
 
 /* Fill `pyramid` (ssr_hiz_floats floats) with levels 0..top of the depth
- * pyramid the hierarchical march traverses (Appendix D, the hierarchical
- * variant), in inverse depth over each pixel's hit slab [D, D + thickness]:
+ * pyramid the hierarchical march traverses (the library's own acceleration
+ * structure for the hit test of Sec. 3.3; the paper uses none), in inverse
+ * depth over each pixel's hit slab [D, D + thickness]:
  * level 0 is W x H, level L has ceil(W_{L-1}/2) x ceil(H_{L-1}/2) texels and
  * the last level is 1 x 1.  The pair of a level-0 texel is
  * (1/D, 1/(D + thickness)), both correctly rounded float32 quotients (with

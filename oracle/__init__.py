@@ -21,7 +21,8 @@ Modules:
   camera  - pinhole projection and pixel-centre unprojection
   env     - equirect lookup, box mip chain, bilinear/trilinear filtering
   brdf    - GGX D, Schlick F, Smith G1, VNDF sampling, sample weights
-  march   - Hi-Z min pyramid, linear march, Hi-Z march, brute-force checker
+  march   - min-max depth pyramids, linear march (Algorithm 1), the
+            hierarchical march (the build's own traversal), brute-force checker
   shade   - the whole per-pixel estimator (optionally with given hit codes)
   grad    - derivatives of the estimator with the hit codes held fixed,
             by finite differences of the forward

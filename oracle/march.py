@@ -17,8 +17,13 @@ fixed-step version with a depth-match threshold.  Two marches are defined:
   Samples inside the origin pixel are skipped and never count as in front.
 
 * ``march_hiz``: the same criterion, made exact for the piecewise-constant
-  depth heightfield and accelerated by a min-max depth pyramid (the
-  hierarchical tracing that Sec. 3.3 cites).  The view-space ray is clipped
+  depth heightfield and accelerated by a min-max depth pyramid.  The paper
+  marches in fixed steps only (Sec. 3.3, citing a screen-space DDA tracer);
+  this hierarchical traversal is the build's own design, not the paper's.
+  Its result with the iteration cap lifted is pinned to the pyramid-free
+  definition ``brute_force_first_hit``; which rays reach the cap, and after
+  how many iterations, is defined by the traversal below (the same sequence
+  the GPU kernel takes).  The view-space ray is clipped
   to [0, min(max_dist, near-plane crossing)], projected to a screen segment
   P(s) = P0 + s (P1 - P0), s in [0, 1], whose depth 1/((1-s)/d0 + s/d1) is
   monotone in s, and clipped to the screen.  Along the segment the pixels are
@@ -271,8 +276,8 @@ def _gather(pyramid, L, ix, iy):
     return out
 
 
-def brute_force_first_hit(cam, depth, org_pix, V0, Dv, max_dist, thickness):
-    """First hit by scanning every pixel the segment crosses (tiny images only).
+def brute_force_first_hit(cam, depth, org_pix, V0, Dv, max_dist, thickness, bbox=False):
+    """First hit by scanning every pixel the segment crosses (no pyramid).
 
     For each pixel box [i, i+1] x [j, j+1] the s-interval of the clipped
     screen segment inside it is found by slab clipping, without any pyramid.
@@ -280,19 +285,37 @@ def brute_force_first_hit(cam, depth, org_pix, V0, Dv, max_dist, thickness):
     walked in order of entry; the ray's depth over a pixel's interval
     (monotone in s) is compared with the slab [D, D + thickness] under the
     in-front-first rule.  Returns codes.
+
+    With ``bbox`` only the pixels meeting the bounding box of the clipped
+    segment are scanned (a pixel outside it cannot hold a positive-length
+    part of the segment), which makes large images affordable for a few
+    thousand rays; the full scan is for tiny images.
     """
     c = camera.unpack(cam)
     W, H = c["W"], c["H"]
     P0, dP, d0, d1, s_max, valid = screen_segment(cam, org_pix, V0, Dv, max_dist)
     n = V0.shape[0]
     out = np.full(n, HIT_OFFSCREEN, np.int64)
-    jj, ii = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
-    ii = ii.reshape(-1)
-    jj = jj.reshape(-1)
-    D = np.asarray(depth, np.float64).reshape(-1)
+    D2 = np.asarray(depth, np.float64)
+    if not bbox:
+        jj_all, ii_all = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
+        ii_all = ii_all.reshape(-1)
+        jj_all = jj_all.reshape(-1)
+        D_all = D2.reshape(-1)
     for r in range(n):
         if not valid[r]:
             continue
+        if bbox:
+            ends = np.stack([P0[r], P0[r] + min(s_max[r], 1.0) * dP[r]])
+            lo = np.clip(np.floor(ends.min(0)).astype(np.int64) - 1, 0, [W - 1, H - 1])
+            hi = np.clip(np.floor(ends.max(0)).astype(np.int64) + 1, 0, [W - 1, H - 1])
+            jj, ii = np.meshgrid(np.arange(lo[1], hi[1] + 1), np.arange(lo[0], hi[0] + 1),
+                                 indexing="ij")
+            ii = ii.reshape(-1)
+            jj = jj.reshape(-1)
+            D = D2[jj, ii]
+        else:
+            ii, jj, D = ii_all, jj_all, D_all
         lo_s = np.zeros(ii.shape)
         hi_s = np.full(ii.shape, s_max[r])
         for ax, cell in ((0, ii), (1, jj)):
@@ -308,13 +331,18 @@ def brute_force_first_hit(cam, depth, org_pix, V0, Dv, max_dist, thickness):
         crossed &= ~((ii == org_pix[r, 0]) & (jj == org_pix[r, 1]))
         order = np.nonzero(crossed)[0]
         order = order[np.argsort(lo_s[order], kind="stable")]
-        armed = False
-        for k in order:
-            din = _ray_depth(d0[r], d1[r], lo_s[k])
-            dout = _ray_depth(d0[r], d1[r], hi_s[k])
-            lo, hi = min(din, dout), max(din, dout)
-            if hi >= D[k] and lo <= D[k] + thickness and (armed or din < D[k]):
-                out[r] = jj[k] * W + ii[k]
-                break
-            armed = armed or lo < D[k]
+        if order.size == 0:
+            continue
+        # the ray's depth range over each crossed pixel, in order of entry
+        din = _ray_depth(d0[r], d1[r], lo_s[order])
+        dout = _ray_depth(d0[r], d1[r], hi_s[order])
+        lo, hi = np.minimum(din, dout), np.maximum(din, dout)
+        Dk = D[order]
+        # armed before pixel k: the ray was in front in some earlier pixel
+        front = lo < Dk
+        armed = np.concatenate([[False], np.cumsum(front)[:-1] > 0])
+        hit = (hi >= Dk) & (lo <= Dk + thickness) & (armed | (din < Dk))
+        if hit.any():
+            k = order[np.argmax(hit)]
+            out[r] = jj[k] * W + ii[k]
     return out

@@ -43,7 +43,7 @@ HIT_SKIPPED = -5
 
 
 def shade_pixels(cam, gbuf, env_rgb, params, pix, pyramid=None, mips=None,
-                 check_long_form=True, sensitivity=None, replay_hits=None):
+                 check_long_form=True, sensitivity=None, replay_hits=None, hiz_scan=False):
     """Shade the flat pixel indices ``pix``.
 
     ``gbuf``: dict with ``depth`` [H][W], ``normal_rough``, ``albedo_metal``,
@@ -55,6 +55,11 @@ def shade_pixels(cam, gbuf, env_rgb, params, pix, pyramid=None, mips=None,
     This is the estimator with the hit selection held fixed, the form whose
     derivatives the adjoint computes (the march itself is not
     differentiable).
+
+    With ``hiz_scan`` the hierarchical march is replaced by its pyramid-free
+    definition, ``march.brute_force_first_hit`` (no iteration cap; the
+    iteration counts are then 0): the exact first crossing the traversal
+    must find whenever it is not capped.
 
     With ``sensitivity=eps`` (radians) the result also holds ``bound`` [n][3]:
     how far each output can move when every direction the estimator looks up
@@ -74,7 +79,7 @@ def shade_pixels(cam, gbuf, env_rgb, params, pix, pyramid=None, mips=None,
     rad = np.asarray(gbuf["radiance"], np.float64).reshape(-1, 4)
     if mips is None:
         mips = env.build_mips(env_rgb)
-    if pyramid is None and int(params["march"]) == 1 and replay_hits is None:
+    if pyramid is None and int(params["march"]) == 1 and replay_hits is None and not hiz_scan:
         pyramid = (march.hiz_pyramid(depth), march.hiz_max_pyramid(depth))
 
     i = pix % W
@@ -168,6 +173,10 @@ def shade_pixels(cam, gbuf, env_rgb, params, pix, pyramid=None, mips=None,
             cc, it = march.march_linear(cam, depth, org, V0r, Dv, float(params["step_len"]),
                                         int(params["max_steps"]), float(params["max_dist"]),
                                         float(params["thickness"]))
+        elif hiz_scan:
+            cc = march.brute_force_first_hit(cam, depth, org, V0r, Dv, float(params["max_dist"]),
+                                             float(params["thickness"]), bbox=True)
+            it = np.zeros_like(cc)
         else:
             cc, it = march.march_hiz(cam, pyramid, org, V0r, Dv, int(params["max_steps"]),
                                      float(params["max_dist"]), float(params["thickness"]))

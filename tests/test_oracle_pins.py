@@ -237,6 +237,69 @@ def test_env_mips_are_block_means():
     assert env.roughness_level(mips, 1.0) == 5.0 and env.roughness_level(mips, 0.0) == 0.0
 
 
+def _texel_centre_dir(x, y, we, he):
+    """Unit direction to the centre of texel (x, y) of a we x he equirect
+    level (u = (x + 1/2)/we, v = (y + 1/2)/he; u = 1/2 + atan2(d.x, -d.z)/(2 pi),
+    v = theta/pi)."""
+    phi = ((x + 0.5) / we - 0.5) * 2 * math.pi
+    th = (y + 0.5) / he * math.pi
+    return np.array([math.sin(th) * math.sin(phi), math.cos(th), -math.sin(th) * math.cos(phi)])
+
+
+def test_roughness_level_interior_values():
+    """lambda = log2(1 + rho) lambda_max (Sec. 3.2, SampleEnvMap) at interior
+    roughness values whose logarithm is known by hand: rho = sqrt(2) - 1 gives
+    lambda_max / 2, rho = 2^(1/4) - 1 a quarter, rho = 2^(3/4) - 1 three
+    quarters.  A linear reading (rho lambda_max) gives 0.414, 0.189 and 0.682
+    of lambda_max and fails."""
+    mips = env.build_mips(np.ones((64, 128, 3)))       # lambda_max = 6
+    assert env.lambda_max(mips) == 6
+    for rho, frac in ((math.sqrt(2.0) - 1.0, 0.5), (2 ** 0.25 - 1.0, 0.25), (2 ** 0.75 - 1.0, 0.75)):
+        assert abs(env.roughness_level(mips, rho) - 6 * frac) < 1e-12
+
+
+def test_trilinear_blends_adjacent_levels_by_the_fraction():
+    """A level-0 checkerboard of 1 and 3 (8 x 4) has the constant 2 on every
+    level above it.  At a level-0 texel centre holding 1, E_lambda at
+    lambda = 1/4 is (1 - 1/4) * 1 + 1/4 * 2 = 1.25 (a swapped blend gives
+    1.75); at lambda = 1/2 it is 1.5 for a texel holding 1 and 2.5 for one
+    holding 3; at lambda >= 1 it is 2."""
+    he, we = 4, 8
+    yy, xx = np.meshgrid(np.arange(he), np.arange(we), indexing="ij")
+    img = np.where((xx + yy) % 2 == 0, 1.0, 3.0)[..., None] * np.ones(3)
+    mips = env.build_mips(img)
+    assert np.all(mips[1] == 2.0) and np.all(mips[2] == 2.0)
+    d1 = _texel_centre_dir(2, 0, we, he)[None]            # (2 + 0) even: holds 1
+    d3 = _texel_centre_dir(3, 2, we, he)[None]            # (3 + 2) odd: holds 3
+    assert np.allclose(env.bilinear(img, d1), 1.0, rtol=0, atol=1e-12)
+    assert np.allclose(env.trilinear(mips, d1, np.array([0.25])), 1.25, rtol=0, atol=1e-12)
+    assert np.allclose(env.trilinear(mips, d1, np.array([0.5])), 1.5, rtol=0, atol=1e-12)
+    assert np.allclose(env.trilinear(mips, d3, np.array([0.5])), 2.5, rtol=0, atol=1e-12)
+    assert np.allclose(env.trilinear(mips, d3, np.array([1.7])), 2.0, rtol=0, atol=1e-12)
+
+
+def test_direct_term_at_interior_roughness_closed_form():
+    """The whole direct term c_d = (1 - m) a E_lambda(n) through the pixel
+    estimator: normal aimed at a level-0 texel centre of the checkerboard
+    above, rho = 2^(1/8) - 1 so lambda = 2 * 1/8 = 1/4, metallic 0.25,
+    albedo (0.2, 0.4, 0.8), specular off: c_d = 0.75 a (0.75 * 1 + 0.25 * 2)."""
+    he, we = 4, 8
+    yy, xx = np.meshgrid(np.arange(he), np.arange(we), indexing="ij")
+    img = np.where((xx + yy) % 2 == 0, 1.0, 3.0)[..., None] * np.ones(3)
+    cam = dict(width=2, height=1, pos=np.zeros(3), rot=np.eye(3), fx=2.0, fy=2.0, cx=1.0,
+               cy=0.5, z_near=0.01)
+    n = _texel_centre_dir(2, 0, we, he)
+    g = dict(depth=np.full((1, 2), 2.0),
+             normal_rough=np.tile(np.r_[n, 2 ** 0.125 - 1.0], (1, 2, 1)),
+             albedo_metal=np.tile(np.array([0.2, 0.4, 0.8, 0.25]), (1, 2, 1)),
+             radiance=np.zeros((1, 2, 4)))
+    p = dict(spp=1, march=1, max_steps=64, step_len=0.1, max_dist=10.0, thickness=0.05, seed=0,
+             frame=0, flags=2)
+    out = shade.shade_frame(cam, g, img, p)["out"]
+    want = 0.75 * np.array([0.2, 0.4, 0.8]) * (0.75 * 1.0 + 0.25 * 2.0)
+    assert np.allclose(out, want, rtol=0, atol=1e-12)
+
+
 # --------------------------------------------------------------- pyramid ---
 
 @pytest.mark.parametrize("h,w", [(1, 1), (1, 7), (5, 3), (9, 13), (16, 16), (33, 17)])
@@ -294,6 +357,9 @@ def test_hiz_march_equals_brute_force(h, w):
         pyr = (march.hiz_pyramid(depth), march.hiz_max_pyramid(depth))
         for thick in (0.05, 0.5):
             want = march.brute_force_first_hit(cam, depth, org, V0, Dv, 6.0, thick)
+            # the bounding-box restriction drops only pixels the segment cannot cross
+            assert np.array_equal(
+                march.brute_force_first_hit(cam, depth, org, V0, Dv, 6.0, thick, bbox=True), want)
             got, it = march.march_hiz(cam, pyr, org, V0, Dv, 10 ** 6, 6.0, thick)
             assert np.array_equal(got, want)
             capped, itc = march.march_hiz(cam, pyr, org, V0, Dv, 12, 6.0, thick)
