@@ -134,13 +134,24 @@ struct HizRay {
 
 // The next pixel after moving to segment parameter se across the boundary
 // of a cell whose exits are ex, ey (crossing at sx, sy): on a crossed axis the
-// first pixel past the boundary, on the other axis the pixel the point lies in.
+// first pixel past the boundary, on the other axis the pixel the point lies
+// in, kept between the current pixel and the cell's last pixel in the
+// direction of travel.  (Near a cell corner the rounded coordinate can fall
+// on the far side of a boundary the ray has just crossed on that axis; two
+// such steps back, one per axis, would repeat forever.  The point lies in
+// the cell it leaves, and a ray's pixel index never goes back on either
+// axis, so the clamp only removes rounding.)
+// the median of three (one v_med3_i32)
+__device__ __forceinline__ int med3i(int a, int b, int c) {
+    return max(min(a, b), min(max(a, b), c));
+}
+
 __device__ __forceinline__ void next_pixel(const HizRay& r, float se, float sx, float sy, int ex,
                                            int ey, int& nx, int& ny) {
     const bool kx = sx == se, ky = sy == se;
     const int v = static_cast<int>(floorf(fmaf(se, kx ? r.dPy : r.dPx, kx ? r.P0y : r.P0x)));
-    nx = kx ? ex + r.xp - 1 : v;
-    ny = ky ? ey + r.yp - 1 : v;
+    nx = kx ? ex + r.xp - 1 : med3i(v, r.ix, ex - r.xp);
+    ny = ky ? ey + r.yp - 1 : med3i(v, r.iy, ey - r.yp);
 }
 
 // Start a ray and take its first iteration.  At s = 0 the ray lies in the
@@ -171,6 +182,8 @@ __device__ __forceinline__ bool hiz_start(const ShadeArgs& a, HizRay& r, int i, 
     r.L = 0;
     r.armed = 0.0f;
     r.it = 1;
+    r.ix = i;
+    r.iy = j;
     const int ex = i + r.xp, ey = j + r.yp;
     const float sx = fmaf(static_cast<float>(ex), r.inv_dx, r.bx);
     const float sy = fmaf(static_cast<float>(ey), r.inv_dy, r.by);

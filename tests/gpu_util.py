@@ -106,19 +106,39 @@ def rel_err(gpu, ref, floor=1e-6):
     return np.abs(gpu - ref) / np.maximum(np.abs(ref), floor)
 
 
+# Codes of samples that never march: invalid direction or back-facing
+# pixel, background pixel, specular switched off.
+NO_MARCH = (-2, -3, -5)
+
+# Share of agreeing pixels that must be within plain rel_tol relative error,
+# counted over the well-conditioned ones (the oracle's own bound for a
+# DIR_EPS direction error below rel_tol |ref|).  Every agreeing pixel, well
+# conditioned or not, must be within rel_tol |ref| + bound.
+MIN_PLAIN = 0.999
+
+
 def compare(gpu_out, gpu_hits, ref_out, ref_hits, label="", ref_bound=None, rel_tol=1e-4):
-    """Hit agreement over valid samples and per-pixel error on pixels whose
-    samples all agree.  With ``ref_bound`` (the oracle's first-order output
-    change for a DIR_EPS direction error) also the excess of each pixel's
-    error over rel_tol * |ref| + bound (``excess_max`` <= 0 passes).
+    """Hit agreement and per-pixel error.  Hit agreement counts the samples
+    that march on either side (codes other than -2, -3, -5 on the GPU or in
+    the oracle); the non-marching samples are compared on their own.  The
+    per-pixel error is taken on pixels whose samples all agree.  With
+    ``ref_bound`` (the oracle's first-order output change for a DIR_EPS
+    direction error) also the excess of each pixel's error over
+    rel_tol * |ref| + bound (``excess_max`` <= 0 passes) and the plain share
+    over well-conditioned pixels (bound <= rel_tol |ref| in every channel).
     Returns a dict of statistics (printed)."""
-    valid = ref_hits != oracle.shade.HIT_BACKGROUND
-    agree = (gpu_hits == ref_hits)
-    frac = agree[valid].mean() if valid.any() else 1.0
+    nm_ref = np.isin(ref_hits, NO_MARCH)
+    nm_gpu = np.isin(gpu_hits, NO_MARCH)
+    marched = ~(nm_ref & nm_gpu)
+    agree = gpu_hits == ref_hits
+    frac = agree[marched].mean() if marched.any() else 1.0
+    nm = nm_ref | nm_gpu
+    nm_frac = agree[nm].mean() if nm.any() else 1.0
     pix_ok = agree.all(axis=-1)
     rel = rel_err(gpu_out, ref_out).max(axis=-1)
     r = rel[pix_ok]
-    stats = dict(samples=int(valid.sum()), hit_agreement=float(frac),
+    stats = dict(samples_marched=int(marched.sum()), hit_agreement=float(frac),
+                 no_march_agreement=float(nm_frac),
                  pixels_compared=int(pix_ok.sum()), pixels=int(pix_ok.size),
                  rel_p50=float(np.quantile(r, 0.5)) if r.size else 0.0,
                  rel_p99=float(np.quantile(r, 0.99)) if r.size else 0.0,
@@ -130,7 +150,13 @@ def compare(gpu_out, gpu_hits, ref_out, ref_hits, label="", ref_bound=None, rel_
         allowed = rel_tol * np.abs(ref_out) + ref_bound
         ex = (err - allowed)[pix_ok]
         stats["excess_max"] = float(ex.max()) if ex.size else 0.0
-        stats["bound_rel_p50"] = float(np.quantile((ref_bound / np.maximum(np.abs(ref_out), 1e-6))[pix_ok], 0.5)) if ex.size else 0.0
+        brel = (ref_bound / np.maximum(np.abs(ref_out), 1e-6)).max(axis=-1)
+        well = (brel <= rel_tol) & pix_ok
+        stats["bound_dominated"] = float(1.0 - well.sum() / max(1, pix_ok.sum()))
+        rw = rel[well]
+        stats["well_conditioned"] = int(well.sum())
+        stats["frac_within_1e4_well"] = float((rw <= rel_tol).mean()) if rw.size else 1.0
+        stats["rel_max_well"] = float(rw.max()) if rw.size else 0.0
     print(f"[{label}] " + " ".join(f"{k}={v:.6g}" if isinstance(v, float) else f"{k}={v}"
                                    for k, v in stats.items()), flush=True)
     return stats
