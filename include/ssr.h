@@ -63,6 +63,8 @@ typedef enum {
     SSR_E_BUDGET = -6, /* the session's device-memory budget cannot hold it     */
     SSR_E_BUSY = -7,   /* the session is serving (or stopping): not allowed now  */
     SSR_E_TICKET = -8, /* no such request (never submitted, or already retired) */
+    SSR_E_SCRATCH = -9,/* the frame's workspace exceeds the static scratch buffer
+                          of ssr_shade_static (SSR_STATIC_SCRATCH_BYTES)          */
     SSR_PENDING = 1    /* the request has not finished yet                       */
 } ssr_status;
 
@@ -182,6 +184,41 @@ void ssr_ctx_destroy(ssr_ctx* ctx);
 int ssr_shade(ssr_ctx* ctx, const ssr_camera* cam, const ssr_gbuffer* gbuf,
               const ssr_env* env, const ssr_params* params, float* out_rgb,
               int32_t* out_hits, int32_t* out_steps, void* stream);
+
+/* Bytes of the static device scratch buffer that ssr_shade_static uses as
+ * its workspace (192 MiB, on every device the library runs on, held until
+ * the process ends). */
+#define SSR_STATIC_SCRATCH_BYTES (192ll << 20)
+
+/* ssr_shade for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  The
+ * same frame as ssr_shade (the same kernels; bit for bit the same outputs),
+ * with no context and no allocation: nothing here calls hipMalloc, hipFree or
+ * an allocating library routine.  Its workspace lives in a file-scope
+ * static device array of SSR_STATIC_SCRATCH_BYTES per device: the trace
+ * kernel's work counter (256 B), then, unless the caller supplies them, the
+ * depth pyramid (gbuf->hiz NULL: ssr_hiz_floats(W, H) floats), the
+ * per-sample hit codes (out_hits NULL: ssr_codes_count(W, H, spp,
+ * SSR_CODES_TILED) int32, or the public layout when out_steps is given) and
+ * the env mip chain (env->mips NULL: ssr_env_mips_floats floats), each
+ * starting on a 256-byte boundary.  A frame whose workspace does not fit is
+ * refused with SSR_E_SCRATCH before anything is enqueued (1920 x 1080 at
+ * 16 spp fits with every part in scratch, about 180 MB; 3840 x 2160 at
+ * 16 spp needs the caller's out_hits).
+ * The device is the calling thread's current HIP device (hipSetDevice);
+ * `stream` must belong to it.  The first call on a device looks up the
+ * array's address there (hipGetSymbolAddress) and checks that it is a
+ * gfx950 device (SSR_E_DEVICE otherwise); ssr_ctx_create does the same for
+ * its device, so a caller can do it before any graph capture.
+ * Every call on one device shares that device's array, which keeps the last
+ * call's contents; the counter is reset by a kernel at the start of each
+ * frame and the other parts are written before they are read.  Calls whose
+ * work overlaps on one device (different streams, or different host
+ * threads, without ordering between them) race on the array: order them.
+ * Other arguments, outputs and errors as ssr_shade. */
+int ssr_shade_static(const ssr_camera* cam, const ssr_gbuffer* gbuf, const ssr_env* env,
+                     const ssr_params* params, float* out_rgb, int32_t* out_hits,
+                     int32_t* out_steps, void* stream);
 
 /* The march half of ssr_shade (Sec. 3.3 sampling; the march of Appendix D,
  * Algorithm 1, or the library's hierarchical march, per params->march): write

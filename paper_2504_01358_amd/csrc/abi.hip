@@ -3,6 +3,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 
 #include "kernels.h"
@@ -106,6 +107,57 @@ void camera_args(const ssr_camera* cam, ssr::ShadeArgs* a) {
 
 }  // namespace
 
+// ------------------------------------------------ static scratch buffer --
+//
+// The workspace of ssr_shade_static: one array per device (each device that
+// loads the library holds its own copy until the process ends).  Host code
+// never uses the array's name as an address: its device address is looked up
+// once per device with hipGetSymbolAddress and kept in `g_static`.
+static __device__ __align__(256) char scratch[SSR_STATIC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+
+struct StaticDevice {
+    char* ptr = nullptr;   // device address of `scratch` on this device
+    int cu_count = 0;
+    int status = 1;        // 1: not looked up yet; else SSR_OK or the error
+};
+
+std::mutex g_static_mu;
+StaticDevice g_static[kMaxDevices];
+
+// Look up the scratch array on `device` (made current by the caller) once,
+// checking that the device is a gfx950.
+int static_device(int device, StaticDevice* out) {
+    if (device < 0 || device >= kMaxDevices) return SSR_E_DEVICE;
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    StaticDevice& d = g_static[device];
+    if (d.status == 1) {
+        hipDeviceProp_t prop;
+        void* p = nullptr;
+        if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+            (void)hipGetLastError();
+            return SSR_E_HIP;   // not cached: a later call may succeed
+        }
+        if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+            d.status = SSR_E_DEVICE;
+        } else if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return SSR_E_HIP;
+        } else {
+            d.ptr = static_cast<char*>(p);
+            d.cu_count = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 1;
+            d.status = SSR_OK;
+        }
+    }
+    *out = d;
+    return d.status;
+}
+
+}  // namespace
+
 namespace ssr {
 
 int fill_args(const ssr_camera* cam, const ssr_gbuffer* g, const ssr_env* env, const ssr_params* p,
@@ -166,6 +218,7 @@ const char* ssr_status_string(int status) {
         case SSR_E_BUDGET: return "the session's device-memory budget cannot hold it";
         case SSR_E_BUSY: return "not allowed while the session is serving or stopping";
         case SSR_E_TICKET: return "no such request";
+        case SSR_E_SCRATCH: return "the frame's workspace exceeds the static scratch buffer";
         case SSR_PENDING: return "pending";
         default: return "unknown status";
     }
@@ -202,6 +255,12 @@ int ssr_ctx_create(int device, ssr_ctx** out) {
         delete c;
         return SSR_E_NOMEM;
     }
+    // (the static scratch buffer's address on this device, for
+    // ssr_shade_static, looked up here so that it happens outside any graph
+    // capture; a failure is not the context's: ssr_shade_static tries again
+    // and reports it)
+    StaticDevice sd;
+    (void)static_device(device, &sd);
     *out = c;
     return SSR_OK;
 }
@@ -391,6 +450,67 @@ int ssr_shade(ssr_ctx* ctx, const ssr_camera* cam, const ssr_gbuffer* g, const s
         codes = ctx->codes;
     }
     st = trace(ctx, g, p, &a, hiz_lay, codes, out_steps, s);
+    if (st != SSR_OK) return st;
+    a.out = out_rgb;
+    return hip_status(ssr::launch_resolve(a, g->dtype, s));
+}
+
+int ssr_shade_static(const ssr_camera* cam, const ssr_gbuffer* g, const ssr_env* env,
+                     const ssr_params* p, float* out_rgb, int32_t* out_hits, int32_t* out_steps,
+                     void* stream) {
+    ssr::ShadeArgs a;
+    ssr::EnvLayout env_lay;
+    ssr::HizLayout hiz_lay;
+    int st = ssr::fill_args(cam, g, env, p, true, &a, &env_lay, &hiz_lay);
+    if (st != SSR_OK) return st == 1 ? SSR_OK : st;
+    if (!out_rgb) return SSR_E_ARG;
+    int device = -1;
+    if (hipGetDevice(&device) != hipSuccess) {
+        (void)hipGetLastError();
+        return SSR_E_HIP;
+    }
+    StaticDevice sd;
+    st = static_device(device, &sd);
+    if (st != SSR_OK) return st;
+    // the workspace: counter, then whatever the caller does not supply
+    auto align = [](int64_t n) { return (n + 255) / 256 * 256; };
+    int64_t off = 256;
+    int64_t o_hiz = -1, o_codes = -1, o_mips = -1;
+    if (p->march == SSR_MARCH_HIZ && !g->hiz) {
+        o_hiz = off;
+        off += align(hiz_lay.total * 16);
+    }
+    if (!out_hits) {
+        if (!out_steps) a.flags |= SSR_CODES_TILED;
+        o_codes = off;
+        off += align(ssr_codes_count(cam->width, cam->height, p->spp, a.flags) * 4);
+    }
+    if (!env->mips) {
+        o_mips = off;
+        off += align(env_lay.total * 16);
+    }
+    if (off > SSR_STATIC_SCRATCH_BYTES) return SSR_E_SCRATCH;
+    // (from here on the array is addressed through sd.ptr only)
+    char* base = sd.ptr;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    a.tile_counter = reinterpret_cast<int*>(base);
+    if (o_mips >= 0) {
+        st = hip_status(ssr::launch_env_mips(env->rgb, env_lay, reinterpret_cast<float4*>(base + o_mips), s));
+        if (st != SSR_OK) return st;
+        a.env = reinterpret_cast<const float4*>(base + o_mips);
+    } else {
+        a.env = reinterpret_cast<const float4*>(env->mips);
+    }
+    a.hiz = reinterpret_cast<const float4*>(g->hiz);
+    if (o_hiz >= 0) {
+        float4* hiz = reinterpret_cast<float4*>(base + o_hiz);
+        st = hip_status(ssr::launch_hiz(g->depth, hiz_lay, p->thickness, hiz, s));
+        if (st != SSR_OK) return st;
+        a.hiz = hiz;
+    }
+    a.codes = o_codes >= 0 ? reinterpret_cast<int32_t*>(base + o_codes) : out_hits;
+    a.steps = out_steps;
+    st = hip_status(ssr::launch_trace(a, g->dtype, p->march, sd.cu_count, s));
     if (st != SSR_OK) return st;
     a.out = out_rgb;
     return hip_status(ssr::launch_resolve(a, g->dtype, s));

@@ -26,7 +26,8 @@ SYMBOLS = ("ssr_ctx_create", "ssr_ctx_destroy", "ssr_shade", "ssr_trace", "ssr_r
            "ssr_philox4x32_10", "ssr_status_string", "ssr_session_create",
            "ssr_session_add_scene", "ssr_session_request_bytes", "ssr_session_submit",
            "ssr_session_poll", "ssr_session_wait", "ssr_session_get_stats",
-           "ssr_session_destroy", "ssr_depth_normals", "ssr_brdf_lut", "ssr_first_pass", "ssr_codes_count")
+           "ssr_session_destroy", "ssr_depth_normals", "ssr_brdf_lut", "ssr_first_pass", "ssr_codes_count",
+           "ssr_shade_static")
 
 PENDING = 1
 CODES_TILED = 8      # per-sample buffers tile-major over 8 x 8 pixel tiles
@@ -104,6 +105,8 @@ def _load():
     lib.ssr_ctx_destroy.restype = None
     lib.ssr_shade.argtypes = [vp, P(Camera), P(GBuffer), P(Env), P(Params), vp, vp, vp, vp]
     lib.ssr_shade.restype = ctypes.c_int
+    lib.ssr_shade_static.argtypes = [P(Camera), P(GBuffer), P(Env), P(Params), vp, vp, vp, vp]
+    lib.ssr_shade_static.restype = ctypes.c_int
     lib.ssr_trace.argtypes = [vp, P(Camera), P(GBuffer), P(Params), vp, vp, vp]
     lib.ssr_trace.restype = ctypes.c_int
     lib.ssr_resolve.argtypes = [vp, P(Camera), P(GBuffer), P(Env), P(Params), vp, vp, vp]
@@ -317,6 +320,31 @@ class Context:
                              _stream(stream, depth.device))
         _check(st, "ssr_resolve")
         return out
+
+
+STATIC_SCRATCH_BYTES = 192 << 20   # the static scratch buffer of shade_static, per device
+E_SCRATCH = -9
+
+
+def shade_static(camera, depth, normal_rough, albedo_metal, radiance, env, params, out,
+                 env_mips=None, hiz=None, hits=None, steps=None, stream=None):
+    """``ssr_shade_static``: one frame with no context and no device
+    allocation in the library (its workspace is a static device array of
+    STATIC_SCRATCH_BYTES).  ``out`` [H][W][3] float32 is required (the
+    binding allocates nothing either); the current device is the one used."""
+    cam = camera if isinstance(camera, Camera) else make_camera(camera)
+    prm = params if isinstance(params, Params) else make_params(params)
+    g = Context._gbuf(cam, depth, normal_rough, albedo_metal, radiance, hiz)
+    e = Context._env(env, env_mips)
+    _dev_tensor(out, "out", torch.float32, (cam.height, cam.width, 3))
+    for name, t in (("hits", hits), ("steps", steps)):
+        if t is not None:
+            _dev_tensor(t, name, torch.int32, codes_shape(cam.width, cam.height, prm.spp, prm.flags))
+    st = lib.ssr_shade_static(ctypes.byref(cam), ctypes.byref(g), ctypes.byref(e),
+                              ctypes.byref(prm), _ptr(out), _ptr(hits), _ptr(steps),
+                              _stream(stream, depth.device))
+    _check(st, "ssr_shade_static")
+    return out
 
 
 def _shade_backward(self, camera, depth, normal_rough, albedo_metal, radiance, env, params, hits,

@@ -36,7 +36,7 @@ def declared_functions():
 
 def test_every_declared_symbol_is_exported(lib):
     names = declared_functions()
-    assert len(names) == 24, names
+    assert len(names) == 25, names
     raw = ctypes.CDLL(LIB)
     for n in names:
         assert hasattr(raw, n), n
@@ -99,7 +99,7 @@ def test_sizes_and_status_strings(lib):
         assert lib.hiz_floats(w, h) == hiz(w, h)
     assert lib.hiz_floats(16384, 16384) == 0
     assert lib.hiz_floats(0, 5) == 0 and lib.hiz_floats(16385, 2) == 0
-    for s in (0, -1, -2, -3, -4, -5):
+    for s in (0, -1, -2, -3, -4, -5, -6, -7, -8, -9, 1):
         assert lib.status_string(s) and lib.status_string(s) != "unknown status"
     assert lib.status_string(-99) == "unknown status"
 
@@ -157,5 +157,28 @@ def test_host_side_argument_checks(lib):
     assert raw.ssr_depth_normals(byref(ok), None, 3, None, None) == -2
     ok.width, ok.height = 4, 4
     assert raw.ssr_depth_normals(byref(ok), None, 0, None, None) == -1    # null buffers
+    # the allocation-free entry point: its argument checks come before it
+    # looks at any device (null structures, a bad camera, an empty image)
+    assert raw.ssr_shade_static(None, byref(g), byref(e), byref(p), None, None, None, None) == -1
+    assert raw.ssr_shade_static(byref(cam), None, byref(e), byref(p), None, None, None, None) == -1
+    ok.width, ok.height = 0, 0
+    p0 = lib.Params(1, 1, 64, 0.1, 10.0, 0.05, 0, 0, 0)
+    g0 = lib.GBuffer(None, None, None, None, 0, None)
+    e0 = lib.Env(ctypes.c_void_p(16), 8, 4, None)
+    assert raw.ssr_shade_static(byref(ok), byref(g0), byref(e0), byref(p0), None, None, None, None) == 0
     raw.ssr_session_destroy(None)
     raw.ssr_ctx_destroy(None)
+
+
+def test_static_scratch_size_matches_header(lib):
+    text = open(HEADER).read()
+    m = re.search(r"#define SSR_STATIC_SCRATCH_BYTES \((\d+)ll << (\d+)\)", text)
+    assert m, "SSR_STATIC_SCRATCH_BYTES not found"
+    assert int(m.group(1)) << int(m.group(2)) == lib.STATIC_SCRATCH_BYTES
+    # the headline frame (1920 x 1080, 16 samples) fits with every part in
+    # scratch: counter, pyramid, tile-major codes, the 512 x 256 mip chain
+    al = lambda n: (n + 255) // 256 * 256
+    need = (256 + al(lib.hiz_floats(1920, 1080) * 4)
+            + al(lib.lib.ssr_codes_count(1920, 1080, 16, lib.CODES_TILED) * 4)
+            + al(lib.env_mips_floats(512, 256) * 4))
+    assert need <= lib.STATIC_SCRATCH_BYTES
