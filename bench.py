@@ -65,24 +65,37 @@ def upload(scene, dtype, dev):
     return t
 
 
-# Algorithmic work model of one frame (the method's own reads, writes and
-# arithmetic; not what the implementation happens to issue), split between
-# the trace kernel (sampling and march) and the resolve kernel (shading).
+# Roofline of the path: HBM bandwidth on the method's algorithmic bytes, with
+# the VALU rate beside it.  Per frame (P pixels, S samples each):
 #
-# Bytes.  Trace: every pixel's depth (4 B); a non-background pixel its
-# normal/roughness record (16 B FP32, 8 B FP16/BF16); per march iteration the
-# pyramid texel it reads (hierarchical: the cell's pair and its parent's,
-# 16 B; linear: one depth, 4 B).  Resolve: every pixel's RGB output (12 B); a
-# background pixel one environment texel (12 B), any other pixel its two
-# material records (32 B FP32, 16 B FP16/BF16); per ray one radiance read
-# (12 B FP32 or 6 B FP16 at a hit pixel, 12 B of environment otherwise).  The
-# per-sample hit codes passed between the two are the split's own traffic
-# and not counted.  The pyramid build reads the depth once and writes one
-# 16 B texel per pyramid texel.
+#   B = P (B_g + 12 + 16/3) + sum over samples of (4 n_iter + B_r)
 #
-# Operations: 32-bit lane operations of the method's own formulation (an
-# FMA, a compare, a select, a transcendental instruction each count one).
-# Trace:
+#   B_g   G-buffer bytes per pixel: depth 4 + normal/roughness 16 +
+#         albedo/metallic 16 + radiance 12 = 48 (FP32), 4 + 8 + 8 + 6 = 26
+#         (FP16 / BF16; depth stays FP32)
+#   12    the FP32 RGB output
+#   16/3  the depth pyramid: 4 B of depth read + 4/3 B of pyramid written
+#   4     one 4 B depth per march iteration (n_iter iterations of the sample)
+#   B_r   the radiance read of a sample that reaches one: 12 at a hit (FP32;
+#         6 FP16 / BF16) or of environment on a miss (-1, -4); 0 otherwise
+#
+# The trace kernel processes every pixel and sample of the frame, so its
+# figure is B over its average launch time; the frame's is B over the frame
+# time.  The trace's own share (depth 4 + normal 16 (8) per pixel, 4 B per
+# iteration) is reported beside them.
+#
+# VALU: about 200 lane operations per sample (Philox, the visible-normal
+# sample, the segment, the weight and the sum) plus 25 per march iteration.
+# Peak: 157.3 TFLOP/s FP32 vector counts an FMA as two flops and a packed
+# instruction as two lanes; single 32-bit lane operations issue at
+# 256 CUs x 64 lanes x 2.4 GHz.
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+ALU_OPS_PER_SAMPLE = 200
+ALU_OPS_PER_ITER = 25
+
+# A finer model of the implementation's own operation counts (an FMA, a
+# compare, a select, a transcendental instruction each count one), kept as a
+# separately named figure:
 OPS_PER_HIZ_ITER = 54     # two cells (the cell and its parent), each: cell index 2,
                           # exit parameter per axis 3 (x2), nearer exit 1, ray
                           # inverse depth at the exit 1, texel address 2, front
@@ -97,23 +110,13 @@ OPS_PER_SEGMENT = 35      # view direction 9, end point 8, projection 10, screen
                           # deltas and inverse depths 8
 OPS_PER_PIXEL_SETUP = 48  # un-projection 3, view vector 17, normal 7, clamps 2,
                           # frame 10, local view vector 9
-# Resolve:
-OPS_PER_WEIGHT = 29       # Schlick Fresnel 8, Smith G1 6, product 3; compensated sum 12
-OPS_PER_HIT = 2           # radiance texel address
-OPS_PER_MISS = 47         # equirect angles 25, texel coordinates 6, weights 4, blend 12
-OPS_PER_PIXEL_SHADE = 85  # F0 3; direct diffuse: level 3, angles 25, two bilinear
-                          # lookups 44, blend 3, albedo 4; output 3
-# Peak: 157.3 TFLOP/s FP32 vector counts an FMA as two flops and a packed
-# instruction as two lanes; single 32-bit lane operations issue at
-# 256 CUs x 64 lanes x 2.4 GHz.
-VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 
 
 def work_model(scene, hits, steps, dtype):
-    """Algorithmic bytes and operations of the trace and resolve kernels and
-    bytes of the pyramid build, from the frame's hit codes and iteration
-    counts."""
+    """Algorithmic bytes and operations of one frame from its hit codes and
+    iteration counts (the model above)."""
     P = scene.width * scene.height
+    S = hits.shape[-1]
     half = dtype != "f32"
     n_iter = int(steps.sum(dtype=np.int64))
     rays = (hits >= 0) | (hits == -1) | (hits == -4)  # samples that reach a radiance lookup
@@ -121,26 +124,18 @@ def work_model(scene, hits, steps, dtype):
     n_rays = int(rays.sum())
     n_env = n_rays - n_hit
     fg = int((hits[..., 0] != -3).sum())
-    hiz = scene.params["march"] == 1
     n_drawn = int((hits != -3).sum() - (hits == -5).sum())
-    trace_bytes = P * 4 + fg * (8 if half else 16) + (16 if hiz else 4) * n_iter
-    trace_ops = ((OPS_PER_HIZ_ITER if hiz else OPS_PER_LINEAR_STEP) * n_iter
-                 + OPS_PER_SAMPLE * n_drawn + OPS_PER_SEGMENT * n_rays + OPS_PER_PIXEL_SETUP * fg)
-    resolve_bytes = (P * 12 + fg * (16 if half else 32) + (P - fg) * 12
-                     + (6 if half else 12) * n_hit + 12 * n_env)
-    resolve_ops = (OPS_PER_WEIGHT * n_rays + OPS_PER_HIT * n_hit + OPS_PER_MISS * n_env
-                   + (OPS_PER_PIXEL_SETUP + OPS_PER_PIXEL_SHADE) * fg)
-    texels, w, h = 0, scene.width, scene.height
-    while True:
-        texels += w * h
-        if w == 1 and h == 1:
-            break
-        w, h = (w + 1) // 2, (h + 1) // 2
-    hiz_bytes = P * 4 + 16 * int(texels)
-    return dict(bytes_trace=trace_bytes, ops_trace=trace_ops, bytes_resolve=resolve_bytes,
-                ops_resolve=resolve_ops, bytes_hiz=hiz_bytes,
-                mean_iters=n_iter / max(1, n_rays), hit_frac=n_hit / max(1, n_rays),
-                iterations=n_iter, rays=n_rays)
+    B_g = 26 if half else 48
+    b_hit = 6 if half else 12
+    frame_bytes = P * (B_g + 12) + (P * 16) // 3 + 4 * n_iter + b_hit * n_hit + 12 * n_env
+    trace_bytes = P * (4 + (8 if half else 16)) + 4 * n_iter
+    alu_ops = ALU_OPS_PER_SAMPLE * P * S + ALU_OPS_PER_ITER * n_iter
+    hiz = scene.params["march"] == 1
+    impl_ops = ((OPS_PER_HIZ_ITER if hiz else OPS_PER_LINEAR_STEP) * n_iter
+                + OPS_PER_SAMPLE * n_drawn + OPS_PER_SEGMENT * n_rays + OPS_PER_PIXEL_SETUP * fg)
+    return dict(frame_bytes=frame_bytes, trace_bytes=trace_bytes, alu_ops=alu_ops,
+                impl_ops_trace=impl_ops, mean_iters=n_iter / max(1, n_rays),
+                hit_frac=n_hit / max(1, n_rays), iterations=n_iter, rays=n_rays)
 
 
 COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "trace_hiz_kernel_c2_1080p_16spp_counters.md")
@@ -219,7 +214,7 @@ def time_gpu(ctx, scene, dtype, steps, warmup, dev, mips):
     ctx.shade(cam, t["depth"], t["normal_rough"], t["albedo_metal"], t["radiance"], t["env"], prm,
               env_mips=mips, out=out, hits=hits, steps=nst, stream=stream)
     torch.cuda.synchronize()
-    hits_np, steps_np = hits.cpu().numpy(), nst.cpu().numpy()
+    hits_np, steps_np, out_np = hits.cpu().numpy(), nst.cpu().numpy(), out.cpu().numpy()
     del hits, nst
 
     for _ in range(warmup):
@@ -244,7 +239,41 @@ def time_gpu(ctx, scene, dtype, steps, warmup, dev, mips):
     return dict(ms_per_step=total_ms / steps, wall_ms_per_step=1e3 * wall / steps,
                 frame_ms_p50=float(np.median(frame_ms)), frame_ms_p99=float(np.quantile(frame_ms, 0.99)),
                 trace_ms=float(np.mean(trace_ms)), resolve_ms=float(np.mean(resolve_ms)),
-                hiz_ms=float(np.mean(hiz_ms)), **work)
+                hiz_ms=float(np.mean(hiz_ms)), image=out_np, codes=hits_np,
+                step_fn=step, **work)
+
+
+def time_precision(runs, frames=100, warmup=10, block=10):
+    """Frame times of the storage types side by side: blocks of `block`
+    frames of each type in turn (so that clock and thermal drift fall on all
+    of them alike) until each has `frames` timed frames, after `warmup`
+    untimed frames each.  Per type: p50, p10 and p90 of the frame time and
+    the p50 of the trace and resolve kernels, from HIP events on the stream
+    the kernels run on."""
+    import torch
+    stream = torch.cuda.current_stream()
+    for fn in runs.values():
+        for _ in range(warmup):
+            fn()
+    times = {dt: [[], [], []] for dt in runs}
+    while min(len(v[0]) for v in times.values()) < frames:
+        for dt, fn in runs.items():
+            evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(block)]
+            for e in evs:
+                fn(e)
+            stream.synchronize()
+            for e in evs:
+                times[dt][0].append(e[0].elapsed_time(e[3]))
+                times[dt][1].append(e[1].elapsed_time(e[2]))
+                times[dt][2].append(e[2].elapsed_time(e[3]))
+    out = {}
+    for dt, (fr, tr, rs) in times.items():
+        fr = np.array(fr)
+        out[dt] = {"frames": int(fr.size), "frame_ms_p50": float(np.median(fr)),
+                   "frame_ms_p10": float(np.quantile(fr, 0.1)),
+                   "frame_ms_p90": float(np.quantile(fr, 0.9)),
+                   "trace_ms_p50": float(np.median(tr)), "resolve_ms_p50": float(np.median(rs))}
+    return out
 
 
 def time_linear(ctx, scene, dev, mips, reps=20):
@@ -291,18 +320,29 @@ def _oracle_rows(args):
            if sc.params["march"] == 1 else None)
     t0 = time.perf_counter()
     n = 0
+    outs, codes = [], []
     for r in rows:
         pix = np.arange(r * sc.width, (r + 1) * sc.width)
-        oracle.shade_pixels(sc.camera, g, sc.env, sc.params, pix, pyramid=pyr, mips=mips)
+        res = oracle.shade_pixels(sc.camera, g, sc.env, sc.params, pix, pyramid=pyr, mips=mips)
+        outs.append(res["out"])
+        codes.append(res["hits"].astype(np.int32))
         n += pix.size
-    return n, time.perf_counter() - t0
+    return n, time.perf_counter() - t0, rows, outs, codes
+
+
+# Worker processes of the CPU baseline: one per core the process may run on,
+# at most 16 (the host share of one GPU on the machines this runs on).
+CPU_WORKERS_MAX = 16
 
 
 def cpu_baseline(cfg, scene, row_stride):
     """The FP64 oracle on every row_stride-th row of the frame, one worker
-    process per available core (row-interleaved), wall-clock timed."""
+    process per available core (row-interleaved), wall-clock timed.  Returns
+    the figure and the oracle's image and hit codes of those rows (for the
+    error report of the GPU frames)."""
     import multiprocessing as mp
-    cores = min(len(os.sched_getaffinity(0)), 16)
+    affinity = len(os.sched_getaffinity(0))
+    cores = min(affinity, CPU_WORKERS_MAX)
     rows = list(range(0, scene.height, row_stride))
     chunks = [rows[k::cores] for k in range(cores)]
     chunks = [c for c in chunks if c]
@@ -314,10 +354,42 @@ def cpu_baseline(cfg, scene, row_stride):
     busy = max(r[1] for r in res)
     pixels = sum(r[0] for r in res)
     rays = pixels * scene.params["spp"]
-    return dict(value=rays / busy / 1e6, unit="Mrays/s", cores=len(chunks), kind="oracle",
-                sample=f"every {row_stride}th row of the frame ({len(rows)} rows, {pixels} pixels, "
-                       f"{rays} rays), FP64 NumPy, {len(chunks)} worker processes; "
-                       f"{busy:.1f} s compute, {wall:.1f} s wall incl. start-up")
+    ref = {}
+    for _, _, rr, outs, codes in res:
+        for r, o, c in zip(rr, outs, codes):
+            ref[r] = (o, c)
+    order = sorted(ref)
+    sample = dict(rows=np.array(order), out=np.stack([ref[r][0] for r in order]),
+                  hits=np.stack([ref[r][1] for r in order]))
+    fig = dict(value=rays / busy / 1e6, unit="Mrays/s", cores=len(chunks), kind="oracle",
+               affinity_cores=affinity,
+               sample=f"every {row_stride}th row of the frame ({len(rows)} rows, {pixels} pixels, "
+                      f"{rays} rays), FP64 NumPy, {len(chunks)} worker processes (one per core "
+                      f"of the {affinity} this process may use, at most {CPU_WORKERS_MAX}); "
+                      f"{busy:.1f} s compute, {wall:.1f} s wall incl. start-up")
+    return fig, sample
+
+
+def error_report(gpu_image, gpu_codes, sample, tol):
+    """The GPU frame against the FP64 oracle on the CPU baseline's rows:
+    hit agreement over samples that march on either side, per-pixel relative
+    error (p50, p99, max) over pixels whose samples all agree, the share of
+    them within `tol`, and the image-level relative L1 over non-background
+    pixels."""
+    g = gpu_image[sample["rows"]].astype(np.float64).reshape(-1, 3)
+    h = gpu_codes[sample["rows"]].reshape(g.shape[0], -1)
+    o = sample["out"].reshape(-1, 3)
+    oh = sample["hits"].reshape(g.shape[0], -1)
+    nm = np.isin(h, (-2, -3, -5)) & np.isin(oh, (-2, -3, -5))
+    agree = h == oh
+    ok = agree.all(axis=1)
+    rel = (np.abs(g - o) / np.maximum(np.abs(o), 1e-6)).max(axis=1)[ok]
+    fg = oh[:, 0] != -3
+    l1 = float(np.abs(g - o)[fg].sum() / max(np.abs(o)[fg].sum(), 1e-30))
+    return {"pixels": int(g.shape[0]), "hit_agreement": float(agree[~nm].mean()),
+            "pixels_all_agree": float(ok.mean()), "rel_p50": float(np.quantile(rel, 0.5)),
+            "rel_p99": float(np.quantile(rel, 0.99)), "rel_max": float(rel.max()),
+            f"frac_within_{tol:g}": float((rel <= tol).mean()), "image_rel_l1": l1}
 
 
 def time_backward(ctx, dev, reps=20):
@@ -519,11 +591,11 @@ def main():
     scene = scenes.make_scene(args.config)
     # the CPU leg runs first, before anything initialises the GPU, so its
     # worker processes start from a process with no device state
-    cpu = None
+    cpu = sample = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(args.config, scene, args.cpu_rows or 8)
-        print(f"bench: oracle {cpu['value']:.3f} Mrays/s on {cpu['cores']} cores",
-              file=sys.stderr, flush=True)
+        cpu, sample = cpu_baseline(args.config, scene, args.cpu_rows or 8)
+        print(f"bench: oracle {cpu['value']:.3f} Mrays/s on {cpu['cores']} cores "
+              f"({cpu['affinity_cores']} available)", file=sys.stderr, flush=True)
 
     serve_data = None
     if not args.no_serve:
@@ -557,11 +629,12 @@ def main():
         del src, dst, flush
     rays = scene.width * scene.height * scene.params["spp"]
     r32 = res["f32"]
-    trace_s, resolve_s = r32["trace_ms"] * 1e-3, r32["resolve_ms"] * 1e-3
-    ops_rate = r32["ops_trace"] / trace_s / 1e12
+    trace_s, frame_s = r32["trace_ms"] * 1e-3, r32["ms_per_step"] * 1e-3
+    B = r32["frame_bytes"]
+    P = scene.width * scene.height
     line = {
         "metric": "Mrays/s + ms/frame at 1080p 16spp (FP32 vs FP16 G-buf); p50/p99 serve latency",
-        "value": rays / (r32["ms_per_step"] * 1e-3) / 1e6,
+        "value": rays / frame_s / 1e6,
         "unit": "Mrays/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -578,29 +651,56 @@ def main():
                                "G-buffer; plane + 40 spheres + 60 boxes; env 512x256 lognormal(0,2)",
                    "width": scene.width, "height": scene.height, "spp": scene.params["spp"],
                    "march": "hiz", "max_steps": scene.params["max_steps"]},
-        "roofline": {"bound": "alu", "achieved": ops_rate, "peak": VALU_PEAK_TOPS,
-                     "unit": "Tops/s", "frac": ops_rate / VALU_PEAK_TOPS,
+        # the frame's algorithmic bytes (every pixel and sample, which the
+        # trace kernel processes) over the trace kernel's average duration
+        "roofline": {"bound": "hbm", "achieved": B / trace_s / 1e9, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": B / trace_s / 1e9 / HBM_PEAK_GBS,
                      "traffic": measured_traffic() if args.config == "c2" else None,
                      "kernel": "trace_hiz_kernel<f32>", "kernel_ms": r32["trace_ms"],
-                     "algorithmic_ops": r32["ops_trace"],
+                     "algorithmic_bytes": B,
+                     "bytes_model": "P (B_g + 12 + 16/3) + sum over samples (4 n_iter + B_r), "
+                                    "B_g 48, B_r 12 (hit or env miss)",
                      "march_iterations": r32["iterations"], "rays": r32["rays"],
                      "mean_iterations_per_ray": r32["mean_iters"],
-                     "hbm_algorithmic_bytes": r32["bytes_trace"],
-                     "hbm_gbs": r32["bytes_trace"] / trace_s / 1e9},
-        "resolve": {"kernel": "resolve_kernel<f32>", "kernel_ms": r32["resolve_ms"],
-                    "alu_tops": r32["ops_resolve"] / resolve_s / 1e12,
-                    "alu_frac": r32["ops_resolve"] / resolve_s / 1e12 / VALU_PEAK_TOPS,
-                    "hbm_gbs": r32["bytes_resolve"] / resolve_s / 1e9,
-                    "hbm_frac": r32["bytes_resolve"] / resolve_s / 1e9 / HBM_PEAK_GBS},
+                     "frame": {"ms": r32["ms_per_step"], "gbs": B / frame_s / 1e9,
+                               "frac": B / frame_s / 1e9 / HBM_PEAK_GBS},
+                     "trace_share": {"bytes": r32["trace_bytes"],
+                                     "gbs": r32["trace_bytes"] / trace_s / 1e9,
+                                     "frac": r32["trace_bytes"] / trace_s / 1e9 / HBM_PEAK_GBS},
+                     "alu": {"ops": r32["alu_ops"], "model": "200 per sample + 25 per iteration",
+                             "tops": r32["alu_ops"] / trace_s / 1e12, "peak": VALU_PEAK_TOPS,
+                             "frac": r32["alu_ops"] / trace_s / 1e12 / VALU_PEAK_TOPS},
+                     "alu_impl_model": {"ops": r32["impl_ops_trace"],
+                                        "tops": r32["impl_ops_trace"] / trace_s / 1e12,
+                                        "frac": r32["impl_ops_trace"] / trace_s / 1e12 / VALU_PEAK_TOPS}},
+        "resolve_ms": r32["resolve_ms"],
         "frame_ms_p50": r32["frame_ms_p50"], "frame_ms_p99": r32["frame_ms_p99"],
         "hiz_build_ms": r32["hiz_ms"],
-        "hiz_build_gbs": r32["bytes_hiz"] / (r32["hiz_ms"] * 1e-3) / 1e9,
+        "hiz_build_gbs": P * 16 / 3 / (r32["hiz_ms"] * 1e-3) / 1e9,
     }
-    for dt in ("f16", "bf16"):
-        if dt in res:
-            line[dt] = {"value": rays / (res[dt]["ms_per_step"] * 1e-3) / 1e6,
-                        "ms_per_step": res[dt]["ms_per_step"], "trace_ms": res[dt]["trace_ms"],
-                        "resolve_ms": res[dt]["resolve_ms"]}
+    if not args.no_variants:
+        prec = time_precision({dt: res[dt]["step_fn"] for dt in res}, frames=max(100, args.steps))
+        line["precision"] = prec
+        for dt in ("f16", "bf16"):
+            line[dt] = {"value": rays / (prec[dt]["frame_ms_p50"] * 1e-3) / 1e6,
+                        "ms_per_step": res[dt]["ms_per_step"], **prec[dt],
+                        "frame_bytes": res[dt]["frame_bytes"],
+                        "hbm_frac_frame": res[dt]["frame_bytes"] / (prec[dt]["frame_ms_p50"] * 1e-3)
+                        / 1e9 / HBM_PEAK_GBS}
+        f32p, f16p = prec["f32"], prec["f16"]
+        print(f"bench: frame p50 f32 {f32p['frame_ms_p50']:.4f} ms (p10-p90 "
+              f"{f32p['frame_ms_p10']:.4f}-{f32p['frame_ms_p90']:.4f}), f16 "
+              f"{f16p['frame_ms_p50']:.4f} ms ({f16p['frame_ms_p10']:.4f}-{f16p['frame_ms_p90']:.4f})",
+              file=sys.stderr, flush=True)
+    if sample is not None:
+        line["error_vs_oracle"] = {
+            dt: error_report(res[dt]["image"], res[dt]["codes"], sample, 1e-4 if dt == "f32" else 1e-3)
+            for dt in res}
+        line["error_vs_oracle"]["sample"] = ("the CPU baseline's rows; the oracle fed the FP32 "
+                                             "G-buffer (for f16/bf16: the quantisation's own effect)")
+    for r in res.values():
+        for k in ("image", "codes", "step_fn"):
+            r.pop(k, None)
     line["linear"] = time_linear(ctx, scene, dev, mips)
     print(f"bench: linear march {line['linear']['ms_per_step']:.3f} ms/frame", file=sys.stderr,
           flush=True)

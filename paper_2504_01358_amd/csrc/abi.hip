@@ -92,6 +92,8 @@ void camera_args(const ssr_camera* cam, ssr::ShadeArgs* a) {
     memset(a, 0, sizeof(*a));
     a->W = cam->width;
     a->H = cam->height;
+    a->Wf = static_cast<float>(cam->width);
+    a->Hf = static_cast<float>(cam->height);
     for (int k = 0; k < 3; ++k) {
         a->pos[k] = cam->pos[k];
         a->right[k] = cam->rot[k];
@@ -100,6 +102,8 @@ void camera_args(const ssr_camera* cam, ssr::ShadeArgs* a) {
     }
     a->fx = cam->fx;
     a->fy = cam->fy;
+    a->inv_fx = 1.0f / cam->fx;
+    a->inv_fy = 1.0f / cam->fy;
     a->cx = cam->cx;
     a->cy = cam->cy;
     a->z_near = cam->z_near;

@@ -226,7 +226,9 @@ __device__ __forceinline__ float smith_g1(float z, float a2) {
 // Branchless tangent frame (Duff et al., JCGT 2017); sign(+0) = +1.
 __device__ __forceinline__ void onb(V3 n, V3& t, V3& b) {
     const float sign = copysignf(1.0f, n.z);
-    const float a = -1.0f / (sign + n.z);
+    // (the hardware reciprocal, about 1 ulp: the frame stays orthonormal to
+    // that accuracy; sign + n.z >= 1 in magnitude, so it is never near zero)
+    const float a = -__builtin_amdgcn_rcpf(sign + n.z);
     const float bb = n.x * n.y * a;
     t = v3(1.0f + sign * n.x * n.x * a, sign * bb, -sign * n.x);
     b = v3(bb, sign + n.y * n.y * a, -n.y);

@@ -37,9 +37,11 @@ bool make_hiz_layout(int w, int h, HizLayout* out);
 // Everything the shading kernel reads, by value.
 struct ShadeArgs {
     int W, H;
+    float Wf, Hf;             // W and H as floats (kernel arguments: scalar registers)
     float pos[3];
     float right[3], up[3], fwd[3];
     float fx, fy, cx, cy, z_near;
+    float inv_fx, inv_fy;     // 1 / fx, 1 / fy (rounded once, on the host)
     const float* depth;
     const void* normal_rough;
     const void* albedo_metal;

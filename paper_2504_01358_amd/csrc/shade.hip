@@ -100,7 +100,8 @@ struct HizSegment {
 __device__ __forceinline__ HizSegment hiz_segment(const ShadeArgs& a, int i, int j, V3 V0, V3 Dv) {
     HizSegment g;
     float t_end = a.max_dist;
-    if (Dv.z < 0.0f) t_end = fminf(t_end, (a.z_near - V0.z) / Dv.z);
+    // (the near-plane crossing with the hardware reciprocal, about 1 ulp)
+    if (Dv.z < 0.0f) t_end = fminf(t_end, (a.z_near - V0.z) * __builtin_amdgcn_rcpf(Dv.z));
     g.valid = t_end > 0.0f;
     const float EX = V0.x + t_end * Dv.x, EY = V0.y + t_end * Dv.y, EZ = V0.z + t_end * Dv.z;
     const float P0x = static_cast<float>(i) + 0.5f, P0y = static_cast<float>(j) + 0.5f;
@@ -150,19 +151,20 @@ __device__ __forceinline__ void next_pixel(const HizRay& r, float se, float sx, 
                                            int ey, int& nx, int& ny) {
     const bool kx = sx == se, ky = sy == se;
     const int v = static_cast<int>(floorf(fmaf(se, kx ? r.dPy : r.dPx, kx ? r.P0y : r.P0x)));
-    nx = kx ? ex + r.xp - 1 : med3i(v, r.ix, ex - r.xp);
-    ny = ky ? ey + r.yp - 1 : med3i(v, r.iy, ey - r.yp);
+    // (both candidates computed, then selected: no branch)
+    const int cx = ex + r.xp - 1, cy = ey + r.yp - 1;
+    const int vx = med3i(v, r.ix, ex - r.xp), vy = med3i(v, r.iy, ey - r.yp);
+    nx = kx ? cx : vx;
+    ny = ky ? cy : vy;
 }
 
-// Start a ray and take its first iteration.  At s = 0 the ray lies in the
-// slab of its own pixel and of every cell containing it (their nearest depth
-// is at most the pixel's, their farthest depth plus thickness at least its
-// own), so neither the pixel nor its parent can be skipped and the first
-// iteration always crosses the origin pixel into the next one (no test).
-// Returns true when that already ends the ray (it left the segment or the
-// screen, or the cap is one iteration); then `leave` tells which.
-__device__ __forceinline__ bool hiz_start(const ShadeArgs& a, HizRay& r, int i, int j, float dPx,
-                                          float dPy, float iz0, float diz, bool& leave) {
+// The constants of a ray: origin pixel centre, screen delta, its
+// reciprocals and the crossing offsets, the direction of travel, where the
+// segment leaves the screen, and its inverse depths.  State at its start:
+// level 0, not armed, one iteration (the first is taken when it is drawn,
+// see hiz_first).
+__device__ __forceinline__ void hiz_init(const ShadeArgs& a, HizRay& r, int i, int j, float dPx,
+                                         float dPy, float iz0, float diz) {
     r.P0x = static_cast<float>(i) + 0.5f;
     r.P0y = static_cast<float>(j) + 0.5f;
     r.dPx = dPx;
@@ -174,8 +176,8 @@ __device__ __forceinline__ bool hiz_start(const ShadeArgs& a, HizRay& r, int i, 
     r.yp = dPy >= 0.0f ? 1 : 0;
     r.bx = -r.P0x * r.inv_dx;
     r.by = -r.P0y * r.inv_dy;
-    r.s_max = fminf(fminf(fmaf(r.xp ? static_cast<float>(a.W) : 0.0f, r.inv_dx, r.bx),
-                          fmaf(r.yp ? static_cast<float>(a.H) : 0.0f, r.inv_dy, r.by)),
+    r.s_max = fminf(fminf(fmaf(r.xp ? a.Wf : 0.0f, r.inv_dx, r.bx),
+                          fmaf(r.yp ? a.Hf : 0.0f, r.inv_dy, r.by)),
                     1.0f);
     r.iz0 = iz0;
     r.diz = diz;
@@ -184,18 +186,28 @@ __device__ __forceinline__ bool hiz_start(const ShadeArgs& a, HizRay& r, int i, 
     r.it = 1;
     r.ix = i;
     r.iy = j;
-    const int ex = i + r.xp, ey = j + r.yp;
+}
+
+// The first iteration of a ray set up by hiz_init.  At s = 0 the ray lies
+// in the slab of its own pixel and of every cell containing it (their
+// nearest depth is at most the pixel's, their farthest depth plus thickness
+// at least its own), so neither the pixel nor its parent can be skipped and
+// the first iteration always crosses the origin pixel into the next one (no
+// test, no load).  Moves r to that pixel and returns true when the move
+// already ends the ray (it left the segment or the screen).
+__device__ __forceinline__ bool hiz_first(const ShadeArgs& a, HizRay& r) {
+    const int ex = r.ix + r.xp, ey = r.iy + r.yp;
     const float sx = fmaf(static_cast<float>(ex), r.inv_dx, r.bx);
     const float sy = fmaf(static_cast<float>(ey), r.inv_dy, r.by);
     const float se = fminf(fminf(sx, sy), r.s_max);
     int nx, ny;
     next_pixel(r, se, sx, sy, ex, ey, nx, ny);
-    leave = (se >= r.s_max) | (static_cast<unsigned>(nx) >= static_cast<unsigned>(a.W)) |
-            (static_cast<unsigned>(ny) >= static_cast<unsigned>(a.H));
+    const bool leave = (se >= r.s_max) | (static_cast<unsigned>(nx) >= static_cast<unsigned>(a.W)) |
+                       (static_cast<unsigned>(ny) >= static_cast<unsigned>(a.H));
     r.ix = nx;
     r.iy = ny;
     r.s = se;
-    return leave | (a.max_steps <= 1);
+    return leave;
 }
 
 // One iteration, branch-free.  Returns true when the ray is finished; then
@@ -364,12 +376,31 @@ static_assert(kQueueLow - 1 + kGenBatch * 64 <= kQueueCap, "ray queue too small"
 // so that the waves do not all queue on it at the start.
 __global__ void reset_counter_kernel(int* counter, int first) { *counter = first; }
 
+// A queued ray, 28 bytes of LDS: its segment (dPx, dPy, iz0, diz), the
+// segment parameter after its first iteration, the origin pixel with the
+// first step packed beside it (i in bits 0..13, dx + 1 in 14..15, j in
+// 16..29, dy + 1 in 30..31) and where its code goes: the slot (tile S + k)
+// of its 64 codes in the tile-major layout, or the sample index k in the
+// public one.
+__device__ __forceinline__ unsigned pack_origin(int i, int j, int nx, int ny) {
+    return static_cast<unsigned>(i) | (static_cast<unsigned>(nx - i + 1) << 14) |
+           (static_cast<unsigned>(j) << 16) | (static_cast<unsigned>(ny - j + 1) << 30);
+}
+
+// Code index of a queued ray (see code_index).
+template <int TL>
+__device__ __forceinline__ int64_t queued_code_index(const ShadeArgs& a, int i, int j, unsigned slot) {
+    if (TL == 1) return (static_cast<int64_t>(slot) << 6) | ((j & 7) << 3) | (i & 7);
+    return code_index<TL>(a, i, j, static_cast<int>(slot));
+}
+
 template <int DT, int TL>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(SSR_WAVES_PER_EU, 8)))
 void trace_hiz_kernel(const ShadeArgs a) {
     __shared__ int2 lvl[kMaxLevels];
-    __shared__ float4 q_seg[kQueueCap];     // queued rays: (dPx, dPy, iz0, diz)
-    __shared__ int2 q_ray[kQueueCap];       //   and (i | j << 16, sample index)
+    __shared__ float4 q_seg[kQueueCap];     // queued rays: (dPx, dPy, iz0, diz),
+    __shared__ float q_s1[kQueueCap];       //   segment parameter after the first iteration,
+    __shared__ uint2 q_ray[kQueueCap];      //   packed origin and first step, code slot
     const int lane = threadIdx.x;
     {
         // levels past the top (never reached) alias the top texel
@@ -396,7 +427,8 @@ void trace_hiz_kernel(const ShadeArgs a) {
     auto next_unit = [&]() {
         int t = 0;
         if (lane == 0) t = atomicAdd(a.tile_counter, 1);
-        return __shfl(t, 0);
+        // (wave-uniform: the unit arithmetic below stays in scalar registers)
+        return __builtin_amdgcn_readlane(t, 0);
     };
     int tile = 0, kk = 0, kend = 0;
     auto set_unit = [&](int u) {
@@ -438,25 +470,37 @@ void trace_hiz_kernel(const ShadeArgs a) {
             const int fill = fill_code(a, P);
 #pragma unroll 1
             for (int k = kk; k < kk + g; ++k) {
-                int code = fill;
+                int code = fill, iters = 0;
                 bool queue = false;
-                HizSegment sg;
+                HizRay f;
                 if (trace) {
                     const SampleDir d = sample_dir(a, P, q, k);
                     if (d.valid) {
-                        sg = hiz_segment(a, i, j, v3(P.X0, P.Y0, P.D), world_to_view(a, d.l));
-                        queue = sg.valid;
+                        const HizSegment sg =
+                            hiz_segment(a, i, j, v3(P.X0, P.Y0, P.D), world_to_view(a, d.l));
                         code = SSR_HIT_OFFSCREEN;
+                        if (sg.valid) {
+                            // the first iteration here, with every lane busy;
+                            // a ray it already ends is not queued
+                            hiz_init(a, f, i, j, sg.dPx, sg.dPy, sg.iz0, sg.diz);
+                            const bool gone = hiz_first(a, f);
+                            iters = 1;
+                            queue = !gone & (a.max_steps > 1);
+                            code = gone ? SSR_HIT_OFFSCREEN : SSR_HIT_CAP;
+                        }
                     }
                 }
                 const unsigned long long m = __ballot(queue);
                 if (queue) {
                     const int pos = (qt + __popcll(m & below)) & (kQueueCap - 1);
-                    q_seg[pos] = make_float4(sg.dPx, sg.dPy, sg.iz0, sg.diz);
-                    q_ray[pos] = make_int2(i | (j << 16), k);
+                    q_seg[pos] = make_float4(f.dPx, f.dPy, f.iz0, f.diz);
+                    q_s1[pos] = f.s;
+                    q_ray[pos] = make_uint2(pack_origin(i, j, f.ix, f.iy),
+                                            TL == 1 ? static_cast<unsigned>(tile * S + k)
+                                                    : static_cast<unsigned>(k));
                 } else if (inb) {
                     a.codes[code_index<TL>(a, i, j, k)] = code;
-                    if (a.steps) a.steps[code_index<TL>(a, i, j, k)] = 0;
+                    if (a.steps) a.steps[code_index<TL>(a, i, j, k)] = iters;
                 }
                 qt = __builtin_amdgcn_readfirstlane(qt + __popcll(m));
             }
@@ -476,15 +520,18 @@ void trace_hiz_kernel(const ShadeArgs a) {
             if (!active && rank < rem) {
                 const int pos = (qh + rank) & (kQueueCap - 1);
                 const float4 gq = q_seg[pos];
-                const int2 ray = q_ray[pos];
-                const int ri = ray.x & 0xFFFF, rj = ray.x >> 16;
-                dst = a.codes + code_index<TL>(a, ri, rj, ray.y);
+                const float s1 = q_s1[pos];
+                const uint2 ray = q_ray[pos];
+                const int ri = ray.x & 0x3FFF, rj = (ray.x >> 16) & 0x3FFF;
+                hiz_init(a, r, ri, rj, gq.x, gq.y, gq.z, gq.w);
+                r.ix = ri + static_cast<int>((ray.x >> 14) & 3u) - 1;
+                r.iy = rj + static_cast<int>(ray.x >> 30) - 1;
+                r.s = s1;
+                dst = a.codes + queued_code_index<TL>(a, ri, rj, ray.y);
                 active = true;
-                bool leave;
-                if (hiz_start(a, r, ri, rj, gq.x, gq.y, gq.z, gq.w, leave)) finish(false, leave);
             }
             qh = __builtin_amdgcn_readfirstlane(qh + min(nidle, rem));
-            nidle = __popcll(__ballot(!active));
+            nidle = __builtin_amdgcn_readfirstlane(__popcll(__ballot(!active)));
         }
         if (nidle == 64) {
             if (unit >= n_units && qt == qh) break;
@@ -504,7 +551,7 @@ void trace_hiz_kernel(const ShadeArgs a) {
                     if (hiz_step(a, lvl, r, hit, leave)) finish(hit, leave);
                 }
             }
-            nidle = __popcll(__ballot(!active));
+            nidle = __builtin_amdgcn_readfirstlane(__popcll(__ballot(!active)));
         } while (!gen && nidle < want);
         __builtin_amdgcn_wave_barrier();
     }

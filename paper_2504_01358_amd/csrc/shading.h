@@ -91,8 +91,9 @@ __device__ __forceinline__ Pixel setup_pixel(const ShadeArgs& a, int i, int j, i
     const float D = P.bg ? 1.0f : P.D;
     const float4 nr = Texel4<DT>::load(a.normal_rough, q);
     const float4 am = Texel4<DT>::load(a.albedo_metal, q);
-    P.X0 = (static_cast<float>(i) + 0.5f - a.cx) * D / a.fx;
-    P.Y0 = -(static_cast<float>(j) + 0.5f - a.cy) * D / a.fy;
+    // (reciprocal focal lengths from the host: a multiply, not a division)
+    P.X0 = (static_cast<float>(i) + 0.5f - a.cx) * D * a.inv_fx;
+    P.Y0 = -(static_cast<float>(j) + 0.5f - a.cy) * D * a.inv_fy;
     P.wo = -1.0f * normalize(view_to_world(a, P.X0, P.Y0, D));
     P.n = normalize(v3(nr.x, nr.y, nr.z));
     P.rho = fminf(fmaxf(nr.w, 0.0f), 1.0f);
