@@ -511,9 +511,10 @@ def serving_scenes():
     return out, time.perf_counter() - t0
 
 
-def serve_run(data, workspace_bytes, dev):
+def serve_run(data, workspace_bytes, dev, saturated=False, graphs=True):
     """The serving mix through an ssr_session: requests submitted at their
-    arrival times, results collected as they finish."""
+    arrival times (or, saturated, all at once, so that the delivered rate is
+    the session's capacity), results collected as they finish."""
     import torch
 
     import scenes
@@ -525,7 +526,7 @@ def serve_run(data, workspace_bytes, dev):
         px = cam["width"] * cam["height"]
         scene_bound += px * 28 + env.size * 4 + ssr.env_mips_floats(env.shape[1], env.shape[0]) * 4 + 8 * 256
     sess = ssr.Session(0, hbm_budget_bytes=int(scene_bound + workspace_bytes), max_slots=8,
-                       max_bypass=8)
+                       max_bypass=8, graphs=graphs)
     ids, cams = {}, {}
     for k, ri, cam, depth, bits, env, params in data:
         t = {b: torch.from_numpy(bits[b].view(np.int16)).to(dev).view(torch.float16) for b in bits}
@@ -546,7 +547,7 @@ def serve_run(data, workspace_bytes, dev):
 
     t0 = time.perf_counter()
     for n, (ta, k, ri, spp) in enumerate(reqs):
-        while time.perf_counter() - t0 < ta:
+        while not saturated and time.perf_counter() - t0 < ta:
             collect()
             time.sleep(0.0002)
         cam = cams[(k, ri)]
@@ -574,11 +575,14 @@ def serve_run(data, workspace_bytes, dev):
             "admission_wait_ms_p50": float(np.median(queue)),
             "admission_wait_ms_p99": float(np.quantile(queue, 0.99)),
             "value": rays / span / 1e6, "unit": "Mrays/s", "span_s": span,
-            "offered_Mrays_per_s": rays / reqs[-1][0] / 1e6,
+            "offered_Mrays_per_s": (rays / reqs[-1][0] / 1e6) if not saturated else None,
             "peak_concurrent": peak, "scene_bytes": st["scene_bytes"],
             "workspace_bytes": st["arena_bytes"], "dtype": "f16",
+            "frames": "graph replays" if graphs else "direct launches",
             "mix": "8 scenes (100-400 objects) x {640x360,1280x720,1920x1080,3840x2160}, spp "
-                   "{4,16,64}, 512 Poisson arrivals at 200/s, FP16 G-buffers, Hi-Z"}
+                   "{4,16,64}, 512 requests, " + ("all submitted at once" if saturated else
+                                                  "Poisson arrivals at 200/s")
+                   + ", FP16 G-buffers, Hi-Z"}
 
 
 def main():
@@ -714,10 +718,19 @@ def main():
         print(f"bench: backward {line['backward']['backward_ms']:.3f} ms at 800x800 8 spp",
               file=sys.stderr, flush=True)
     if serve_data is not None:
-        line["serve"] = serve_run(serve_data, int(args.serve_workspace_gib * (1 << 30)), dev)
+        ws = int(args.serve_workspace_gib * (1 << 30))
+        line["serve"] = serve_run(serve_data, ws, dev)
         print(f"bench: serve p50 {line['serve']['latency_ms_p50']:.1f} ms p99 "
               f"{line['serve']['latency_ms_p99']:.1f} ms, {line['serve']['value']:.0f} Mrays/s",
               file=sys.stderr, flush=True)
+        # capacity: the same requests all at once, graph replays and direct launches
+        for key, graphs in (("serve_saturated", True), ("serve_saturated_direct", False)):
+            line[key] = serve_run(serve_data, ws, dev, saturated=True, graphs=graphs)
+            print(f"bench: {key} {line[key]['value']:.0f} Mrays/s delivered, p50 "
+                  f"{line[key]['latency_ms_p50']:.1f} ms p99 {line[key]['latency_ms_p99']:.1f} ms",
+                  file=sys.stderr, flush=True)
+        line["serve_saturated"]["vs_fp32_single_frame"] = (
+            line["serve_saturated"]["value"] / line["value"])
     if cpu is not None:
         line["cpu_baseline"] = cpu
     ctx.close()

@@ -378,7 +378,12 @@ const char* ssr_status_string(int status);
  * session's device-memory budget holds its workspace (depth pyramid and
  * per-sample hit codes: ssr_session_request_bytes); admitted requests run
  * concurrently, each on its own stream, and new requests are admitted as
- * earlier ones finish (continuous batching).  Waiting requests are admitted
+ * earlier ones finish (continuous batching).  A frame is a fixed chain of
+ * kernels (depth pyramid, work-counter reset, trace, resolve) whose shape
+ * depends only on the image size, march mode and storage type: each slot
+ * keeps one instantiated HIP graph per such shape class, built on the class's
+ * first request, and replays it for later requests of the class with the
+ * kernel nodes' parameters (buffers, samples, seed, frame, flags) replaced.  Waiting requests are admitted
  * oldest first; one that does not fit may be overtaken by later ones that do,
  * at most max_bypass times.  Each result is the frame ssr_shade renders for
  * the same scene and parameters, bit for bit, whatever else runs beside it.
@@ -389,10 +394,15 @@ const char* ssr_status_string(int status);
  * ------------------------------------------------------------------------ */
 typedef struct ssr_session ssr_session;
 
+/* Session flag: launch each frame's kernels directly instead of replaying a
+ * captured HIP graph (for comparison; the frames are the same). */
+enum { SSR_SESSION_DIRECT = 1u };
+
 typedef struct {
     int64_t hbm_budget_bytes; /* device memory for scenes and request workspaces  */
     int32_t max_slots;        /* requests on the device at once, 1..64            */
     int32_t max_bypass;       /* times the oldest waiting request may be overtaken */
+    uint32_t flags;           /* 0 or SSR_SESSION_DIRECT                           */
 } ssr_session_cfg;
 
 typedef struct {

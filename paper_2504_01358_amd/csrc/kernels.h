@@ -59,6 +59,59 @@ struct ShadeArgs {
     int* tile_counter;        // hierarchical trace: next tile
 };
 
+// One kernel launch with its own copy of the arguments, so that a frame's
+// launches can be run directly or become the kernel nodes of a HIP graph,
+// whose parameters are later replaced launch by launch.
+constexpr int kLaunchMaxArgs = 8;
+constexpr int kLaunchArgBytes = 1024;
+struct Launch {
+    const void* func = nullptr;
+    dim3 grid, block;
+    unsigned shmem = 0;
+    int nargs = 0;
+    unsigned offset[kLaunchMaxArgs] = {};
+    unsigned size = 0;
+    alignas(16) unsigned char data[kLaunchArgBytes];
+    template <class T>
+    void arg(const T& v) {
+        static_assert(alignof(T) <= 16, "argument alignment");
+        size = (size + alignof(T) - 1) / alignof(T) * alignof(T);
+        __builtin_memcpy(data + size, &v, sizeof(T));
+        offset[nargs++] = size;
+        size += sizeof(T);
+    }
+    // pointers to the argument copies (valid while this object lives)
+    void argv(void** out) {
+        for (int i = 0; i < nargs; ++i) out[i] = data + offset[i];
+    }
+};
+static_assert(sizeof(ShadeArgs) + 64 <= kLaunchArgBytes, "launch argument space");
+
+// The launches of a frame, in stream order.
+struct Plan {
+    static constexpr int kMax = 24;
+    Launch l[kMax];
+    int n = 0;
+    Launch& add(const void* func, dim3 grid, dim3 block, unsigned shmem = 0) {
+        Launch& x = l[n++];
+        x.func = func;
+        x.grid = grid;
+        x.block = block;
+        x.shmem = shmem;
+        x.nargs = 0;
+        x.size = 0;
+        return x;
+    }
+};
+hipError_t run_plan(Plan& plan, hipStream_t stream);
+
+// The launches of the pyramid build, the trace (work counter reset, trace)
+// and the resolve, appended to `plan` (the launchers below run exactly these).
+void plan_hiz(const float* depth, const HizLayout& lay, float thickness, float4* pyramid,
+              Plan& plan);
+void plan_trace(const ShadeArgs& args, int dtype, int march, int cu_count, Plan& plan);
+void plan_resolve(const ShadeArgs& args, int dtype, Plan& plan);
+
 hipError_t launch_env_mips(const float* rgb, const EnvLayout& lay, float4* mips,
                            hipStream_t stream);
 hipError_t launch_hiz(const float* depth, const HizLayout& lay, float thickness, float4* pyramid,

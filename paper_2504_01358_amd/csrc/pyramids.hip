@@ -254,27 +254,54 @@ __global__ __launch_bounds__(1024) void hiz_top_kernel(float4* __restrict__ pyr,
     }
 }
 
-hipError_t launch_hiz(const float* depth, const HizLayout& lay, float thickness, float4* pyramid,
-                      hipStream_t stream) {
+void plan_hiz(const float* depth, const HizLayout& lay, float thickness, float4* pyramid,
+              Plan& plan) {
     const int top = lay.levels - 1;
     const int tile_levels = top < kTileLevels ? top : kTileLevels;
     const dim3 grid((lay.w[0] + kTile - 1) / kTile, (lay.h[0] + kTile - 1) / kTile);
-    hipLaunchKernelGGL(hiz_tile_kernel, grid, dim3(256), 0, stream, depth, pyramid, lay, thickness,
-                       tile_levels);
+    Launch& t = plan.add(reinterpret_cast<const void*>(&hiz_tile_kernel), grid, dim3(256));
+    t.arg(depth);
+    t.arg(pyramid);
+    t.arg(lay);
+    t.arg(thickness);
+    t.arg(tile_levels);
     if (top > kTileLevels) {
         const int first = kTileLevels + 1;
         const int64_t need = static_cast<int64_t>(lay.w[first - 1]) * lay.h[first - 1] +
                              static_cast<int64_t>(lay.w[first]) * lay.h[first];
         if (need <= kTopLdsTexels) {
-            hipLaunchKernelGGL(hiz_top_kernel, dim3(1), dim3(1024), need * sizeof(float2), stream,
-                               pyramid, lay, first);
+            Launch& u = plan.add(reinterpret_cast<const void*>(&hiz_top_kernel), dim3(1),
+                                 dim3(1024), static_cast<unsigned>(need * sizeof(float2)));
+            u.arg(pyramid);
+            u.arg(lay);
+            u.arg(first);
         } else {
             for (int L = first; L <= top; ++L) {
                 const int n = lay.w[L] * lay.h[L];
-                hipLaunchKernelGGL(hiz_level_kernel, dim3((n + 255) / 256), dim3(256), 0, stream,
-                                   pyramid, lay, L);
+                Launch& u = plan.add(reinterpret_cast<const void*>(&hiz_level_kernel),
+                                     dim3((n + 255) / 256), dim3(256));
+                u.arg(pyramid);
+                u.arg(lay);
+                u.arg(L);
             }
         }
+    }
+}
+
+hipError_t launch_hiz(const float* depth, const HizLayout& lay, float thickness, float4* pyramid,
+                      hipStream_t stream) {
+    Plan plan;
+    plan_hiz(depth, lay, thickness, pyramid, plan);
+    return run_plan(plan, stream);
+}
+
+hipError_t run_plan(Plan& plan, hipStream_t stream) {
+    for (int k = 0; k < plan.n; ++k) {
+        Launch& x = plan.l[k];
+        void* argv[kLaunchMaxArgs];
+        x.argv(argv);
+        const hipError_t e = hipLaunchKernel(x.func, x.grid, x.block, argv, x.shmem, stream);
+        if (e != hipSuccess) return e;
     }
     return hipGetLastError();
 }

@@ -8,10 +8,20 @@
 // the events, and on completion returns the slot and the workspace and
 // admits whatever waits.  Callers submit and poll from any thread; one mutex
 // guards the session.
+//
+// A frame is the launch plan of ssr_shade (pyramid, counter reset, trace,
+// resolve).  Each slot keeps one instantiated HIP graph per plan structure
+// (the kernel, grid, block and shared memory of every launch: fixed by the
+// image size, march mode and storage type), built from the plan as a chain
+// of kernel nodes on the structure's first request; a later request of the
+// same structure replaces the nodes' parameters in the instantiated graph
+// and replays it.  A slot runs one request at a time, so its graphs are
+// never updated while a launch of them is in flight.
 #include <string.h>
 
 #include <chrono>
 #include <condition_variable>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <new>
@@ -66,9 +76,17 @@ struct ssr_session {
         double t_submit = 0, t_admit = 0, t_done = 0;
         int status = SSR_PENDING;
     };
+    // A plan's structure: per launch, kernel, grid, block, shared memory.
+    using Shape = std::vector<uint64_t>;
+    struct Graph {
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        std::vector<hipGraphNode_t> nodes;   // one kernel node per launch, in plan order
+    };
     struct Slot {
         hipStream_t stream = nullptr;
         hipEvent_t done = nullptr;
+        std::map<Shape, Graph> graphs;
     };
 
     int device = 0;
@@ -97,7 +115,73 @@ struct ssr_session {
     }
     void run();
     int launch(const ssr::serve::Admitted& ad);
+    int replay(Slot& slot, ssr::Plan& plan);
 };
+
+namespace {
+
+ssr_session::Shape shape_of(const ssr::Plan& plan) {
+    ssr_session::Shape k;
+    for (int i = 0; i < plan.n; ++i) {
+        const ssr::Launch& x = plan.l[i];
+        k.push_back(reinterpret_cast<uint64_t>(x.func));
+        k.push_back((static_cast<uint64_t>(x.grid.x) << 32) | x.grid.y);
+        k.push_back((static_cast<uint64_t>(x.block.x) << 32) | x.shmem);
+    }
+    return k;
+}
+
+hipKernelNodeParams node_params(ssr::Launch& x, void** argv) {
+    x.argv(argv);
+    hipKernelNodeParams p = {};
+    p.func = const_cast<void*>(x.func);
+    p.gridDim = x.grid;
+    p.blockDim = x.block;
+    p.sharedMemBytes = x.shmem;
+    p.kernelParams = argv;
+    p.extra = nullptr;
+    return p;
+}
+
+}  // namespace
+
+// Run `plan` on the slot's stream through its graph for the plan's structure
+// (built and instantiated on first use, else updated node by node).
+int ssr_session::replay(Slot& slot, ssr::Plan& plan) {
+    const Shape key = shape_of(plan);
+    auto it = slot.graphs.find(key);
+    if (it == slot.graphs.end()) {
+        Graph g;
+        if (hipGraphCreate(&g.graph, 0) != hipSuccess) return SSR_E_HIP;
+        hipGraphNode_t prev = nullptr;
+        for (int i = 0; i < plan.n; ++i) {
+            void* argv[ssr::kLaunchMaxArgs];
+            const hipKernelNodeParams p = node_params(plan.l[i], argv);
+            hipGraphNode_t node = nullptr;
+            if (hipGraphAddKernelNode(&node, g.graph, prev ? &prev : nullptr, prev ? 1 : 0, &p) !=
+                hipSuccess) {
+                (void)hipGraphDestroy(g.graph);
+                return SSR_E_HIP;
+            }
+            g.nodes.push_back(node);
+            prev = node;
+        }
+        if (hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0) != hipSuccess) {
+            (void)hipGraphDestroy(g.graph);
+            return SSR_E_HIP;
+        }
+        it = slot.graphs.emplace(key, g).first;
+    } else {
+        for (int i = 0; i < plan.n; ++i) {
+            void* argv[ssr::kLaunchMaxArgs];
+            const hipKernelNodeParams p = node_params(plan.l[i], argv);
+            if (hipGraphExecKernelNodeSetParams(it->second.exec, it->second.nodes[i], &p) !=
+                hipSuccess)
+                return SSR_E_HIP;
+        }
+    }
+    return hipGraphLaunch(it->second.exec, slot.stream) == hipSuccess ? SSR_OK : SSR_E_HIP;
+}
 
 // Launch one admitted request on its slot's stream (mutex held).
 int ssr_session::launch(const ssr::serve::Admitted& ad) {
@@ -118,13 +202,23 @@ int ssr_session::launch(const ssr::serve::Admitted& ad) {
     a.codes = reinterpret_cast<int32_t*>(ws + w.codes);
     a.flags |= SSR_CODES_TILED;  // the request's own codes: tile-major, as ssr_shade's
     a.out = rec.req.out_rgb;
+    // the frame's launches: those of ssr_shade with the request's workspace
+    // (the plan lives on the heap: it holds a copy of every launch's arguments)
+    std::unique_ptr<ssr::Plan> plan(new (std::nothrow) ssr::Plan);
+    if (!plan) return SSR_E_NOMEM;
     if (p.march == SSR_MARCH_HIZ) {
         float4* hiz = reinterpret_cast<float4*>(ws + w.hiz);
-        if (ssr::launch_hiz(sc.depth, hl, p.thickness, hiz, s) != hipSuccess) return SSR_E_HIP;
+        ssr::plan_hiz(sc.depth, hl, p.thickness, hiz, *plan);
         a.hiz = hiz;
     }
-    if (ssr::launch_trace(a, sc.dtype, p.march, cu_count, s) != hipSuccess) return SSR_E_HIP;
-    if (ssr::launch_resolve(a, sc.dtype, s) != hipSuccess) return SSR_E_HIP;
+    ssr::plan_trace(a, sc.dtype, p.march, cu_count, *plan);
+    ssr::plan_resolve(a, sc.dtype, *plan);
+    if (cfg.flags & SSR_SESSION_DIRECT) {
+        if (ssr::run_plan(*plan, s) != hipSuccess) return SSR_E_HIP;
+    } else {
+        const int st = replay(slots[ad.slot], *plan);
+        if (st != SSR_OK) return st;
+    }
     if (hipEventRecord(slots[ad.slot].done, s) != hipSuccess) return SSR_E_HIP;
     return SSR_OK;
 }
@@ -180,7 +274,7 @@ int ssr_session_create(int device, const ssr_session_cfg* cfg, ssr_session** out
     if (!out) return SSR_E_ARG;
     *out = nullptr;
     if (!cfg || cfg->hbm_budget_bytes <= 0 || cfg->max_slots < 1 || cfg->max_slots > 64 ||
-        cfg->max_bypass < 0)
+        cfg->max_bypass < 0 || (cfg->flags & ~static_cast<uint32_t>(SSR_SESSION_DIRECT)))
         return SSR_E_ARG;
     int count = 0;
     if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) {
@@ -376,6 +470,10 @@ void ssr_session_destroy(ssr_session* s) {
     if (hipSetDevice(s->device) == hipSuccess) {
         for (auto& sl : s->slots) {
             if (sl.stream) (void)hipStreamSynchronize(sl.stream);
+            for (auto& kv : sl.graphs) {
+                if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+                if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
+            }
             if (sl.done) (void)hipEventDestroy(sl.done);
             if (sl.stream) (void)hipStreamDestroy(sl.stream);
         }

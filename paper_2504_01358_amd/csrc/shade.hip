@@ -596,19 +596,30 @@ __global__ __launch_bounds__(256) void resolve_kernel(const ShadeArgs a) {
     write_out(a, q, direct_term(a, P, i, j), sum);
 }
 
-// One instantiation per storage type and per-sample layout.
-#define SSR_DISPATCH(dtype, tiled)                      \
-    do {                                                \
-        if (tiled) {                                    \
-            if ((dtype) == SSR_F32) SSR_LAUNCH(0, 1);   \
-            else if ((dtype) == SSR_F16) SSR_LAUNCH(1, 1); \
-            else SSR_LAUNCH(2, 1);                      \
-        } else {                                        \
-            if ((dtype) == SSR_F32) SSR_LAUNCH(0, 0);   \
-            else if ((dtype) == SSR_F16) SSR_LAUNCH(1, 0); \
-            else SSR_LAUNCH(2, 0);                      \
-        }                                               \
-    } while (0)
+// The kernel of one storage type (DT) and per-sample layout (TL).
+template <template <int, int> class K>
+const void* pick(int dtype, bool tiled) {
+    if (tiled) {
+        if (dtype == SSR_F32) return K<0, 1>::fn();
+        if (dtype == SSR_F16) return K<1, 1>::fn();
+        return K<2, 1>::fn();
+    }
+    if (dtype == SSR_F32) return K<0, 0>::fn();
+    if (dtype == SSR_F16) return K<1, 0>::fn();
+    return K<2, 0>::fn();
+}
+template <int DT, int TL>
+struct TraceLinearK {
+    static const void* fn() { return reinterpret_cast<const void*>(&trace_linear_kernel<DT, TL>); }
+};
+template <int DT, int TL>
+struct TraceHizK {
+    static const void* fn() { return reinterpret_cast<const void*>(&trace_hiz_kernel<DT, TL>); }
+};
+template <int DT, int TL>
+struct ResolveK {
+    static const void* fn() { return reinterpret_cast<const void*>(&resolve_kernel<DT, TL>); }
+};
 
 int trace_grid(int cu_count, int W, int H) {
     const int n_tiles = ((W + 7) / 8) * ((H + 7) / 8);
@@ -616,37 +627,37 @@ int trace_grid(int cu_count, int W, int H) {
     return n_tiles < resident ? n_tiles : resident;
 }
 
-hipError_t launch_trace(const ShadeArgs& args, int dtype, int march, int cu_count,
-                        hipStream_t stream) {
+void plan_trace(const ShadeArgs& args, int dtype, int march, int cu_count, Plan& plan) {
     const bool tiled = (args.flags & SSR_CODES_TILED) != 0;
     if (march == SSR_MARCH_LINEAR) {
         const dim3 grid(((args.W + 15) / 16) * ((args.H + 15) / 16));
-#define SSR_LAUNCH(DT, TL) \
-    hipLaunchKernelGGL((trace_linear_kernel<DT, TL>), grid, dim3(256), 0, stream, args)
-        SSR_DISPATCH(dtype, tiled);
-#undef SSR_LAUNCH
-        return hipGetLastError();
+        plan.add(pick<TraceLinearK>(dtype, tiled), grid, dim3(256)).arg(args);
+        return;
     }
     const dim3 grid(trace_grid(cu_count, args.W, args.H));
-    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, stream, args.tile_counter,
-                       static_cast<int>(grid.x));
-#define SSR_LAUNCH(DT, TL) \
-    hipLaunchKernelGGL((trace_hiz_kernel<DT, TL>), grid, dim3(64), 0, stream, args)
-    SSR_DISPATCH(dtype, tiled);
-#undef SSR_LAUNCH
-    return hipGetLastError();
+    Launch& r = plan.add(reinterpret_cast<const void*>(&reset_counter_kernel), dim3(1), dim3(1));
+    r.arg(args.tile_counter);
+    r.arg(static_cast<int>(grid.x));
+    plan.add(pick<TraceHizK>(dtype, tiled), grid, dim3(64)).arg(args);
+}
+
+void plan_resolve(const ShadeArgs& args, int dtype, Plan& plan) {
+    const bool tiled = (args.flags & SSR_CODES_TILED) != 0;
+    const dim3 grid(((args.W + 15) / 16) * ((args.H + 15) / 16));
+    plan.add(pick<ResolveK>(dtype, tiled), grid, dim3(256)).arg(args);
+}
+
+hipError_t launch_trace(const ShadeArgs& args, int dtype, int march, int cu_count,
+                        hipStream_t stream) {
+    Plan plan;
+    plan_trace(args, dtype, march, cu_count, plan);
+    return run_plan(plan, stream);
 }
 
 hipError_t launch_resolve(const ShadeArgs& args, int dtype, hipStream_t stream) {
-    const bool tiled = (args.flags & SSR_CODES_TILED) != 0;
-    const dim3 grid(((args.W + 15) / 16) * ((args.H + 15) / 16));
-#define SSR_LAUNCH(DT, TL) \
-    hipLaunchKernelGGL((resolve_kernel<DT, TL>), grid, dim3(256), 0, stream, args)
-    SSR_DISPATCH(dtype, tiled);
-#undef SSR_LAUNCH
-    return hipGetLastError();
+    Plan plan;
+    plan_resolve(args, dtype, plan);
+    return run_plan(plan, stream);
 }
-
-#undef SSR_DISPATCH
 
 }  // namespace ssr

@@ -74,7 +74,10 @@ class Params(ctypes.Structure):
 
 class SessionCfg(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("max_slots", ctypes.c_int32),
-                ("max_bypass", ctypes.c_int32)]
+                ("max_bypass", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+SESSION_DIRECT = 1   # launch frames directly instead of replaying graphs
 
 
 class Request(ctypes.Structure):
@@ -427,9 +430,11 @@ class Session:
     """An ``ssr_session``: resident scenes and a queue of render requests that
     the session admits by device memory and runs concurrently."""
 
-    def __init__(self, device=0, hbm_budget_bytes=8 << 30, max_slots=4, max_bypass=4):
+    def __init__(self, device=0, hbm_budget_bytes=8 << 30, max_slots=4, max_bypass=4,
+                 graphs=True):
         self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
-        cfg = SessionCfg(int(hbm_budget_bytes), int(max_slots), int(max_bypass))
+        cfg = SessionCfg(int(hbm_budget_bytes), int(max_slots), int(max_bypass),
+                         0 if graphs else SESSION_DIRECT)
         h = ctypes.c_void_p()
         _check(lib.ssr_session_create(self.device.index or 0, ctypes.byref(cfg), ctypes.byref(h)),
                "ssr_session_create")

@@ -51,7 +51,7 @@ def test_struct_layout_matches_header(lib, tmp_path):
         "ssr_env": ["rgb", "width", "height", "mips"],
         "ssr_params": ["spp", "march", "max_steps", "step_len", "max_dist", "thickness", "seed",
                        "frame", "flags"],
-        "ssr_session_cfg": ["hbm_budget_bytes", "max_slots", "max_bypass"],
+        "ssr_session_cfg": ["hbm_budget_bytes", "max_slots", "max_bypass", "flags"],
         "ssr_request": ["scene_id", "params", "out_rgb"],
         "ssr_result": ["status", "t_submit", "t_admit", "t_done", "workspace_bytes"],
         "ssr_session_stats": ["scene_bytes", "arena_bytes", "arena_used", "running", "waiting",
@@ -132,11 +132,12 @@ def test_host_side_argument_checks(lib):
     assert raw.ssr_philox4x32_10(None, None, 5, None, None) == -1
     assert raw.ssr_philox4x32_10(None, None, -1, None, None) == -1
     assert raw.ssr_ctx_create(0, None) == -1
-    cfg = lib.SessionCfg(1 << 30, 4, 4)
+    cfg = lib.SessionCfg(1 << 30, 4, 4, 0)
     assert raw.ssr_session_create(0, byref(cfg), None) == -1
     h = ctypes.c_void_p()
-    for bad in (lib.SessionCfg(0, 4, 4), lib.SessionCfg(1 << 30, 0, 4), lib.SessionCfg(1 << 30, 65, 4),
-                lib.SessionCfg(1 << 30, 4, -1)):
+    for bad in (lib.SessionCfg(0, 4, 4, 0), lib.SessionCfg(1 << 30, 0, 4, 0),
+                lib.SessionCfg(1 << 30, 65, 4, 0), lib.SessionCfg(1 << 30, 4, -1, 0),
+                lib.SessionCfg(1 << 30, 4, 4, 2)):
         assert raw.ssr_session_create(0, byref(bad), byref(h)) == -1
     assert raw.ssr_session_submit(None, None, None) == -1
     assert raw.ssr_session_poll(None, 1, None) == -1

@@ -44,13 +44,18 @@ def _intervals_overlap(a, b):
     return a["t_admit"] < b["t_done"] and b["t_admit"] < a["t_done"]
 
 
-def test_results_in_the_mix_equal_results_alone():
+@pytest.mark.parametrize("graphs", [True, False])
+def test_results_in_the_mix_equal_results_alone(graphs):
+    """Each request's frame equals ssr_shade alone, bit for bit: with frames
+    replayed from each slot's graphs (every shape class is built once per
+    slot, then replayed with new node parameters: 18 requests over 3 sizes
+    and 2 march modes on 3 slots) and with frames launched directly."""
     from paper_2504_01358_amd import ssr
     dev = torch.device("cuda", 0)
     ctx = ssr.Context(0)
     scs = _scenes()
     ups = [_upload(sc, dt, dev) for sc, dt in scs]
-    sess = ssr.Session(0, hbm_budget_bytes=256 << 20, max_slots=3, max_bypass=2)
+    sess = ssr.Session(0, hbm_budget_bytes=256 << 20, max_slots=3, max_bypass=2, graphs=graphs)
     ids = [sess.add_scene(sc.camera, u["depth"], u["normal_rough"], u["albedo_metal"],
                           u["radiance"], u["env"]) for (sc, _), u in zip(scs, ups)]
     rng = np.random.default_rng(3)
