@@ -177,8 +177,9 @@ void ssr_ctx_destroy(ssr_ctx* ctx);
  * Sample s of pixel q = j*W + i draws Philox4x32-10 with counter
  * (q, s, frame, 0): u1 = (x0 >> 8) 2^-24 picks the azimuth, u2 = (x1 >> 8) 2^-24
  * the cap height of the visible-normal sample.  width or height 0 is a no-op;
- * W H must leave the depth pyramid below 4 GiB (about 200 Mpixels), else
- * SSR_E_ARG.  In hiz mode the depth pyramid is built in the context's
+ * W H must leave the depth pyramid below 4 GiB (about 200 Mpixels), and
+ * ceil(W/8) ceil(H/8) spp must stay below 2^32 (2^38 codes: more than any
+ * device memory holds), else SSR_E_ARG.  In hiz mode the depth pyramid is built in the context's
  * workspace unless gbuf->hiz supplies it; the env mip chain likewise unless
  * env->mips does.  Both builds run on `stream` before the kernels. */
 int ssr_shade(ssr_ctx* ctx, const ssr_camera* cam, const ssr_gbuffer* gbuf,

@@ -189,6 +189,10 @@ int fill_args(const ssr_camera* cam, const ssr_gbuffer* g, const ssr_env* env, c
     a->hiz_lay = *hiz_lay;
     if (need_env) a->env_lay = *env_lay;
     if (!p) return SSR_OK;
+    // (the trace kernel addresses a (tile, sample) row of 64 codes with 32
+    // bits: refuse frames past that, whose codes no device memory could hold)
+    const int64_t tiles = static_cast<int64_t>((cam->width + 7) / 8) * ((cam->height + 7) / 8);
+    if (tiles * p->spp >= (int64_t(1) << 32)) return SSR_E_ARG;
     a->spp = p->spp;
     a->max_steps = p->max_steps;
     // linear march: samples t_k = k * step_len for k = 1..K, K = min(max_steps,
