@@ -304,10 +304,14 @@ int64_t ssr_hiz_floats(int32_t width, int32_t height);
  * over the smallest depth and one over the largest depth plus thickness of
  * the pixels it covers.  Background (D = +inf) gives (0, 0).  Each texel is
  * stored as four floats, its own pair and then the pair of its parent (the
- * texel (x/2, y/2) one level up; the top texel repeats its own), row-major,
- * level after level.  Depths must be positive, thickness finite and >= 0
- * (else SSR_E_ARG).  Pass the buffer to ssr_shade through ssr_gbuffer.hiz to
- * reuse it with the same thickness. */
+ * texel (x/2, y/2) one level up; the top texel repeats its own), level after
+ * level.  A level of w x h texels takes w * 2 ceil(h/2) slots: its rows go in
+ * pairs, each pair column by column, texel (x, y) in slot
+ * 2 (w floor(y/2) + x) + (y mod 2), so that one 128-byte line holds a 4 x 2
+ * block; the padding slots of a level with odd h are left unwritten.  Depths
+ * must be positive, thickness finite and >= 0 (else SSR_E_ARG).  Pass the
+ * buffer to ssr_shade through ssr_gbuffer.hiz to reuse it with the same
+ * thickness. */
 int ssr_hiz_build(const float* depth, int32_t width, int32_t height, float thickness,
                   float* pyramid, void* stream);
 

@@ -23,13 +23,22 @@ struct EnvLayout {
 
 // Depth pyramid: levels 0..top, each texel a float4: its own pair
 // (1/min D, 1/max(D + thickness)) over the pixels it covers, then its
-// parent's pair (the top texel repeats its own), row-major, level after level.
+// parent's pair (the top texel repeats its own), level after level.  Inside
+// a level the rows go in pairs, each pair stored column by column (texel
+// (x, y) at 2 (w (y / 2) + x) + y % 2; a level with an odd number of rows
+// gets one row of padding), so that a 128 B line holds a 4 x 2 block of
+// texels: rays marching near each other share lines in both directions.
 struct HizLayout {
     int levels;               // top + 1
     int w[kMaxLevels], h[kMaxLevels];
     int offset[kMaxLevels];   // in texels
-    int64_t total;            // texels
+    int64_t total;            // texels, padding included
 };
+
+// Index of texel (x, y) of level L in the layout above.
+__host__ __device__ inline int64_t hiz_index(const HizLayout& lay, int L, int x, int y) {
+    return lay.offset[L] + ((static_cast<int64_t>(y >> 1) * lay.w[L] + x) << 1) + (y & 1);
+}
 
 bool make_env_layout(int w, int h, EnvLayout* out);
 bool make_hiz_layout(int w, int h, HizLayout* out);

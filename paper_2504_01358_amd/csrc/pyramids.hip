@@ -39,7 +39,7 @@ bool make_hiz_layout(int w, int h, HizLayout* out) {
         out->w[L] = lw;
         out->h[L] = lh;
         out->offset[L] = static_cast<int>(off);
-        off += static_cast<int64_t>(lw) * lh;
+        off += static_cast<int64_t>(lw) * ((lh + 1) & ~1);   // rows in pairs
         if (lw == 1 && lh == 1) break;
         lw = (lw + 1) / 2;
         lh = (lh + 1) / 2;
@@ -133,7 +133,7 @@ __device__ __forceinline__ float2 own(const float4* __restrict__ p, int64_t i) {
 // their parent, and complete it if it is the top texel.
 __device__ __forceinline__ void put_level(float4* __restrict__ pyr, const HizLayout& lay, int L,
                                           int x, int y, float2 v) {
-    const int64_t at = lay.offset[L] + static_cast<int64_t>(y) * lay.w[L] + x;
+    const int64_t at = hiz_index(lay, L, x, y);
     put(pyr, at, v);
     if (L == lay.levels - 1) put_parent(pyr, at, v);
     const int cw = lay.w[L - 1], ch = lay.h[L - 1];
@@ -142,7 +142,7 @@ __device__ __forceinline__ void put_level(float4* __restrict__ pyr, const HizLay
 #pragma unroll
         for (int dx = 0; dx < 2; ++dx)
             if (2 * x + dx < cw && 2 * y + dy < ch)
-                put_parent(pyr, lay.offset[L - 1] + static_cast<int64_t>(2 * y + dy) * cw + 2 * x + dx, v);
+                put_parent(pyr, hiz_index(lay, L - 1, 2 * x + dx, 2 * y + dy), v);
 }
 
 __global__ __launch_bounds__(256) void hiz_tile_kernel(const float* __restrict__ depth,
@@ -175,7 +175,7 @@ __global__ __launch_bounds__(256) void hiz_tile_kernel(const float* __restrict__
             const int x = x0 + c, y = y0 + r;
             if (x < W && y < H) {
                 const float2 par = top >= 1 ? m1 : p[r][c];
-                pyr[static_cast<int64_t>(y) * W + x] = make_float4(p[r][c].x, p[r][c].y, par.x, par.y);
+                pyr[hiz_index(lay, 0, x, y)] = make_float4(p[r][c].x, p[r][c].y, par.x, par.y);
             }
         }
     if (tile_levels < 1) return;
@@ -183,7 +183,7 @@ __global__ __launch_bounds__(256) void hiz_tile_kernel(const float* __restrict__
         // level 1: its parent comes from the LDS pass below (or it is the top)
         const int lx = x0 / 2, ly = y0 / 2;
         if (lx < lay.w[1] && ly < lay.h[1]) {
-            const int64_t at = lay.offset[1] + ly * lay.w[1] + lx;
+            const int64_t at = hiz_index(lay, 1, lx, ly);
             put(pyr, at, m1);
             if (top == 1) put_parent(pyr, at, m1);
         }
@@ -208,13 +208,15 @@ __global__ __launch_bounds__(256) void hiz_tile_kernel(const float* __restrict__
     }
 }
 
+// (max, min) over the up-to-four children (2x + dx, 2y + dy) of texel (x, y)
+// of the level above a sw x sh level, read through get(x, y).
 template <typename Get>
 __device__ __forceinline__ float2 children(Get get, int sw, int sh, int x, int y) {
-    float2 v = get((2 * y) * sw + 2 * x);
-    if (2 * x + 1 < sw) v = mm(v, get((2 * y) * sw + 2 * x + 1));
+    float2 v = get(2 * x, 2 * y);
+    if (2 * x + 1 < sw) v = mm(v, get(2 * x + 1, 2 * y));
     if (2 * y + 1 < sh) {
-        v = mm(v, get((2 * y + 1) * sw + 2 * x));
-        if (2 * x + 1 < sw) v = mm(v, get((2 * y + 1) * sw + 2 * x + 1));
+        v = mm(v, get(2 * x, 2 * y + 1));
+        if (2 * x + 1 < sw) v = mm(v, get(2 * x + 1, 2 * y + 1));
     }
     return v;
 }
@@ -224,9 +226,8 @@ __global__ void hiz_level_kernel(float4* __restrict__ pyr, HizLayout lay, int L)
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int dw = lay.w[L];
     if (i >= dw * lay.h[L]) return;
-    const float4* src = pyr + lay.offset[L - 1];
-    const float2 v = children([&](int k) { return own(src, k); }, lay.w[L - 1], lay.h[L - 1], i % dw,
-                              i / dw);
+    const float2 v = children([&](int xx, int yy) { return own(pyr, hiz_index(lay, L - 1, xx, yy)); },
+                              lay.w[L - 1], lay.h[L - 1], i % dw, i / dw);
     put_level(pyr, lay, L, i % dw, i / dw, v);
 }
 
@@ -239,12 +240,14 @@ __global__ __launch_bounds__(1024) void hiz_top_kernel(float4* __restrict__ pyr,
     const int sw0 = lay.w[first - 1], sh0 = lay.h[first - 1];
     float2* a = lds2;
     float2* b = lds2 + sw0 * sh0;
-    for (int i = threadIdx.x; i < sw0 * sh0; i += blockDim.x) a[i] = own(pyr, lay.offset[first - 1] + i);
+    for (int i = threadIdx.x; i < sw0 * sh0; i += blockDim.x)
+        a[i] = own(pyr, hiz_index(lay, first - 1, i % sw0, i / sw0));
     for (int L = first; L < lay.levels; ++L) {
         __syncthreads();
         const int sw = lay.w[L - 1], sh = lay.h[L - 1], dw = lay.w[L], dh = lay.h[L];
         for (int i = threadIdx.x; i < dw * dh; i += blockDim.x) {
-            const float2 v = children([&](int k) { return a[k]; }, sw, sh, i % dw, i / dw);
+            const float2 v = children([&](int xx, int yy) { return a[yy * sw + xx]; }, sw, sh, i % dw,
+                                      i / dw);
             b[i] = v;
             put_level(pyr, lay, L, i % dw, i / dw, v);
         }

@@ -224,9 +224,10 @@ __device__ __forceinline__ bool hiz_step(const ShadeArgs& a, const int2* lvl, Hi
     const int2 lv = lvl[L];
     const int cx = r.ix >> L, cy = r.iy >> L, px = r.ix >> Lp, py = r.iy >> Lp;
     // 32-bit byte offsets from a base held in SGPRs (the pyramid is < 4 GiB;
-    // row index and width are below 2^14, so the 24-bit multiply is exact)
+    // row index and width are below 2^14, so the 24-bit multiply is exact);
+    // texel (cx, cy) of the level at 2 (w (cy / 2) + cx) + cy % 2 (hiz_index)
     const char* base = reinterpret_cast<const char*>(a.hiz);
-    const unsigned oc = (lv.x + __umul24(cy, lv.y) + cx) << 4;
+    const unsigned oc = ((lv.x + ((__umul24(cy >> 1, lv.y) + cx) << 1)) + (cy & 1)) << 4;
     // (1/min D, 1/max(D + th)) of the cell, then of its parent
     const float4 z = *reinterpret_cast<const float4*>(base + oc);
     const float2 zc = make_float2(z.x, z.y), zp = make_float2(z.z, z.w);

@@ -87,12 +87,13 @@ def test_sizes_and_status_strings(lib):
     for bad in ((512, 255), (500, 250), (256, 256), (0, 0), (2 * 16384, 16384)):
         assert lib.env_mips_floats(*bad) == 0
     # depth pyramid, levels 0..top with ceil halving, four floats per texel
-    # (own pair, parent's pair), at most 4 GiB
+    # (own pair, parent's pair), rows stored in pairs (an odd row count padded
+    # by one), at most 4 GiB
     def hiz(w, h):
-        n = w * h
+        n = w * (h + h % 2)
         while w > 1 or h > 1:
             w, h = (w + 1) // 2, (h + 1) // 2
-            n += w * h
+            n += w * (h + h % 2)
         return 4 * n if 16 * n <= 2 ** 32 - 16 else 0
     for w, h in ((1920, 1080), (1, 1), (7, 3), (3840, 2160), (16384, 1), (16384, 12000),
                  (16384, 16384)):
