@@ -130,7 +130,9 @@ struct HizRay {
     int L, ix, iy;        // level and the level-0 pixel containing the current point
     float armed;          // 1 once the ray has been in front of the depth buffer, else 0
                           // (a float: its tests compile to compares, not byte logic)
-    int it;               // iterations so far
+    int deadline;         // the wave's step count at which the ray reaches the
+                          // iteration cap (its own count is kept by the wave)
+    int2 lv;              // (offset, width) of level L, read ahead (see hiz_step)
 };
 
 // The next pixel after moving to segment parameter se across the boundary
@@ -142,6 +144,14 @@ struct HizRay {
 // such steps back, one per axis, would repeat forever.  The point lies in
 // the cell it leaves, and a ray's pixel index never goes back on either
 // axis, so the clamp only removes rounding.)
+// floor(x) as an int, one instruction (v_cvt_flr_i32_f32; x is a pixel
+// coordinate, far inside the int range)
+__device__ __forceinline__ int floor_to_int(float x) {
+    int v;
+    asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(v) : "v"(x));
+    return v;
+}
+
 // the median of three (one v_med3_i32)
 __device__ __forceinline__ int med3i(int a, int b, int c) {
     return max(min(a, b), min(max(a, b), c));
@@ -150,7 +160,7 @@ __device__ __forceinline__ int med3i(int a, int b, int c) {
 __device__ __forceinline__ void next_pixel(const HizRay& r, float se, float sx, float sy, int ex,
                                            int ey, int& nx, int& ny) {
     const bool kx = sx == se, ky = sy == se;
-    const int v = static_cast<int>(floorf(fmaf(se, kx ? r.dPy : r.dPx, kx ? r.P0y : r.P0x)));
+    const int v = floor_to_int(fmaf(se, kx ? r.dPy : r.dPx, kx ? r.P0y : r.P0x));
     // (both candidates computed, then selected: no branch)
     const int cx = ex + r.xp - 1, cy = ey + r.yp - 1;
     const int vx = med3i(v, r.ix, ex - r.xp), vy = med3i(v, r.iy, ey - r.yp);
@@ -161,8 +171,8 @@ __device__ __forceinline__ void next_pixel(const HizRay& r, float se, float sx, 
 // The constants of a ray: origin pixel centre, screen delta, its
 // reciprocals and the crossing offsets, the direction of travel, where the
 // segment leaves the screen, and its inverse depths.  State at its start:
-// level 0, not armed, one iteration (the first is taken when it is drawn,
-// see hiz_first).
+// level 0, not armed (its first iteration is taken when it is drawn, see
+// hiz_first; the caller sets the iteration deadline and the level entry).
 __device__ __forceinline__ void hiz_init(const ShadeArgs& a, HizRay& r, int i, int j, float dPx,
                                          float dPy, float iz0, float diz) {
     r.P0x = static_cast<float>(i) + 0.5f;
@@ -183,7 +193,6 @@ __device__ __forceinline__ void hiz_init(const ShadeArgs& a, HizRay& r, int i, i
     r.diz = diz;
     r.L = 0;
     r.armed = 0.0f;
-    r.it = 1;
     r.ix = i;
     r.iy = j;
 }
@@ -210,24 +219,26 @@ __device__ __forceinline__ bool hiz_first(const ShadeArgs& a, HizRay& r) {
     return leave;
 }
 
-// One iteration, branch-free.  Returns true when the ray is finished; then
-// `hit` tells a hit at (ix, iy) from leaving the screen or the segment (or
-// the iteration cap, which the caller tells by r.it).  `lvl[L]` holds
-// (offset, width) of level L.  A texel holds the cell's pair and its
-// parent's, so one 16 B load serves both; the top texel is its own parent,
-// so the look-ahead needs no special case there (skipping it means leaving
-// the screen, as skipping the top cell does).
-__device__ __forceinline__ bool hiz_step(const ShadeArgs& a, const int2* lvl, HizRay& r, bool& hit,
-                                         bool& leave) {
+// One iteration, branch-free.  `wit` counts the wave's steps, this one
+// included.  Returns true when the ray is finished; then `hit` tells a hit at
+// (ix, iy) from leaving the screen or the segment (or the iteration cap, when
+// neither is set).  `lvl[L]` holds (offset, width) of level L; the entry of
+// the next iteration's level is read as soon as that level is known, so that
+// the next iteration does not start by waiting for it.  A texel holds the
+// cell's pair and its parent's, so one 16 B load serves both; the top texel
+// is its own parent, so the look-ahead needs no special case there (skipping
+// it means leaving the screen, as skipping the top cell does).
+__device__ __forceinline__ bool hiz_step(const ShadeArgs& a, const int2* lvl, HizRay& r, int wit,
+                                         bool& hit, bool& leave) {
     const int L = r.L, Lp = L + 1;
-    ++r.it;
-    const int2 lv = lvl[L];
+    const int2 lv = r.lv;
     const int cx = r.ix >> L, cy = r.iy >> L, px = r.ix >> Lp, py = r.iy >> Lp;
     // 32-bit byte offsets from a base held in SGPRs (the pyramid is < 4 GiB;
     // row index and width are below 2^14, so the 24-bit multiply is exact);
-    // texel (cx, cy) of the level at 2 (w (cy / 2) + cx) + cy % 2 (hiz_index)
+    // texel (cx, cy) of the level at 2 (w (cy / 2) + cx) + cy % 2 (hiz_index;
+    // cy / 2 is py)
     const char* base = reinterpret_cast<const char*>(a.hiz);
-    const unsigned oc = ((lv.x + ((__umul24(cy >> 1, lv.y) + cx) << 1)) + (cy & 1)) << 4;
+    const unsigned oc = ((lv.x + ((__umul24(py, lv.y) + cx) << 1)) + (cy & 1)) << 4;
     // (1/min D, 1/max(D + th)) of the cell, then of its parent
     const float4 z = *reinterpret_cast<const float4*>(base + oc);
     const float2 zc = make_float2(z.x, z.y), zp = make_float2(z.z, z.w);
@@ -265,6 +276,12 @@ __device__ __forceinline__ bool hiz_step(const ShadeArgs& a, const int2* lvl, Hi
     const int ex = up ? epx : ecx, ey = up ? epy : ecy;
     // (a skip is never a hit, so move & !stay is !stay; a skipped cell was
     // in front when its own test says so)
+    // the next level (down two levels, not below 0: a saturating subtract;
+    // at level 0 a stay is the pixel test, and L stays 0 either way; a ray
+    // that leaves or hits no longer needs it)
+    const int Ld = static_cast<int>(__builtin_elementwise_sub_sat(static_cast<unsigned>(L), 2u));
+    const int nL = up ? Lp : (stay ? Ld : L);
+    r.lv = lvl[nL];
     const bool arm = (((up & front_p) | (!up & front_c)) & (se > r.s)) | (test & (nc > zc.x));
     r.armed = arm ? 1.0f : r.armed;
     int nx, ny;
@@ -275,11 +292,8 @@ __device__ __forceinline__ bool hiz_step(const ShadeArgs& a, const int2* lvl, Hi
     r.ix = step ? nx : r.ix;
     r.iy = step ? ny : r.iy;
     r.s = step ? se : r.s;
-    // (down two levels, not below 0: a saturating subtract; at level 0 a
-    // stay is the pixel test, and L stays 0 either way)
-    const int Ld = static_cast<int>(__builtin_elementwise_sub_sat(static_cast<unsigned>(L), 2u));
-    r.L = (step & up) ? Lp : (stay ? Ld : L);
-    return hit | leave | (r.it >= a.max_steps);
+    r.L = nL;
+    return hit | leave | (wit >= r.deadline);
 }
 
 
@@ -453,9 +467,10 @@ void trace_hiz_kernel(const ShadeArgs a) {
     int32_t* dst = nullptr;     // where the marching ray's hit code goes
     bool active = false;
     // a lane's ray ended: write its code (and iteration count)
+    int wit = 0;                // the wave's march steps so far (see HizRay::deadline)
     auto finish = [&](bool hit, bool leave) {
         *dst = hit ? r.iy * a.W + r.ix : (leave ? SSR_HIT_OFFSCREEN : SSR_HIT_CAP);
-        if (a.steps) a.steps[dst - a.codes] = r.it;
+        if (a.steps) a.steps[dst - a.codes] = wit - r.deadline + a.max_steps;
         active = false;
     };
     for (;;) {
@@ -528,6 +543,9 @@ void trace_hiz_kernel(const ShadeArgs a) {
                 r.ix = ri + static_cast<int>((ray.x >> 14) & 3u) - 1;
                 r.iy = rj + static_cast<int>(ray.x >> 30) - 1;
                 r.s = s1;
+                // (one iteration taken: the cap is reached max_steps - 1 steps on)
+                r.deadline = wit + a.max_steps - 1;
+                r.lv = lvl[0];
                 dst = a.codes + queued_code_index<TL>(a, ri, rj, ray.y);
                 active = true;
             }
@@ -547,9 +565,10 @@ void trace_hiz_kernel(const ShadeArgs a) {
         do {
 #pragma unroll
             for (int u = 0; u < kStepUnroll; ++u) {
+                ++wit;
                 if (active) {
                     bool hit, leave;
-                    if (hiz_step(a, lvl, r, hit, leave)) finish(hit, leave);
+                    if (hiz_step(a, lvl, r, wit, hit, leave)) finish(hit, leave);
                 }
             }
             nidle = __builtin_amdgcn_readfirstlane(__popcll(__ballot(!active)));
