@@ -89,7 +89,8 @@ hipError_t launch_env_mips(const float* rgb, const EnvLayout& lay, float4* mips,
 // Pass 1: one 256-thread workgroup per 32 x 32 depth tile writes levels 0..5
 // of that tile.  Each thread reduces a 2 x 2 pixel block to its
 // (1/D, 1/(D + thickness)) level-0 pairs and one level-1 texel in
-// registers; the 16 x 16 level-1 texels go through LDS for levels 2..5.
+// registers; levels 2..4 are wave reductions across lanes, level 5 joins
+// the four waves through LDS (see hiz_tile_kernel).
 // (Small blocks give eight waves per SIMD at 1080p, enough to cover the
 // latency of the depth loads; 4 x 4 blocks ran at two and took 25 % longer.)
 // A texel at level L is the (max, min) of those pairs over the
@@ -145,15 +146,55 @@ __device__ __forceinline__ void put_level(float4* __restrict__ pyr, const HizLay
                 put_parent(pyr, hiz_index(lay, L - 1, 2 * x + dx, 2 * y + dy), v);
 }
 
+// The pair of the lane whose index differs from this lane's in bit M
+// (M = 1, 2: a DPP quad permutation; 4, 8, 16: a swizzle within 32 lanes;
+// 32: a permute across the halves of the wave).
+template <int M>
+__device__ __forceinline__ float lane_xor(float v) {
+    const int x = __float_as_int(v);
+    int y;
+    if constexpr (M == 1) {
+        y = __builtin_amdgcn_update_dpp(x, x, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
+    } else if constexpr (M == 2) {
+        y = __builtin_amdgcn_update_dpp(x, x, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
+    } else if constexpr (M < 32) {
+        y = __builtin_amdgcn_ds_swizzle(x, 0x1F | (M << 10));           // and 0x1F, xor M
+    } else {
+        y = __builtin_amdgcn_ds_bpermute(static_cast<int>((__lane_id() ^ 32u) << 2), x);
+    }
+    return __int_as_float(y);
+}
+
+// (max, min) of the pairs of the lanes that differ from this one in bits
+// M and 2M: the texel one level up of a 2 x 2 group of Morton-ordered lanes.
+template <int M>
+__device__ __forceinline__ float2 reduce_quad(float2 v) {
+    v = mm(v, make_float2(lane_xor<M>(v.x), lane_xor<M>(v.y)));
+    return mm(v, make_float2(lane_xor<2 * M>(v.x), lane_xor<2 * M>(v.y)));
+}
+
+// Levels 0..5 of a 32 x 32 pixel tile, one workgroup of four waves, each
+// wave a 16 x 16 quadrant.  A lane holds the 2 x 2 pixels under one level-1
+// texel; the lanes are in Morton order over the quadrant's 8 x 8 level-1
+// texels (lane bits 0, 2, 4: x; 1, 3, 5: y), so that the texels of level
+// L + 1 are reductions over lanes that differ in bits 2L - 2 and 2L - 1:
+// levels 2, 3 and 4 come from cross-lane exchanges within the wave, level 5
+// from the four waves' level-4 texels through LDS.  Every lane of a group
+// ends with the group's pair, so each texel's parent pair is at hand where
+// the texel is written.
 __global__ __launch_bounds__(256) void hiz_tile_kernel(const float* __restrict__ depth,
                                                        float4* __restrict__ pyr, HizLayout lay,
                                                        float thickness, int tile_levels) {
-    __shared__ float2 lds[2][16 * 16];
+    __shared__ float2 quad[4];
     const int W = lay.w[0], H = lay.h[0];
     const int top = lay.levels - 1;
-    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-    const int x0 = blockIdx.x * kTile + tx * 2;
-    const int y0 = blockIdx.y * kTile + ty * 2;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // the lane's level-1 texel within the quadrant (Morton order)
+    const int a = (lane & 1) | ((lane >> 1) & 2) | ((lane >> 2) & 4);
+    const int b = ((lane >> 1) & 1) | ((lane >> 2) & 2) | ((lane >> 3) & 4);
+    const int q1x = blockIdx.x * 16 + (wave & 1) * 8 + a;   // level-1 texel
+    const int q1y = blockIdx.y * 16 + (wave >> 1) * 8 + b;
+    const int x0 = 2 * q1x, y0 = 2 * q1y;
     float2 p[2][2];
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
@@ -166,45 +207,48 @@ __global__ __launch_bounds__(256) void hiz_tile_kernel(const float* __restrict__
                          : make_float2(-INFINITY, INFINITY);
         }
     }
+    // the pairs of this lane's texels at levels 1..4 (pixels outside the
+    // image count as -inf for the max and +inf for the min)
     const float2 m1 = mm(mm(p[0][0], p[0][1]), mm(p[1][0], p[1][1]));
-    // level 0 with its parents (level 1) from registers
+    const float2 m2 = reduce_quad<1>(m1);
+    const float2 m3 = reduce_quad<4>(m2);
+    const float2 m4 = reduce_quad<16>(m3);
+    if (lane == 0) quad[wave] = m4;
+    __syncthreads();
+    const float2 m5 = mm(mm(quad[0], quad[1]), mm(quad[2], quad[3]));
+    const float2 m[6] = {p[0][0], m1, m2, m3, m4, m5};
+    // level 0: the lane's four pixels (rows y0, y0 + 1 of the row pair y0 / 2:
+    // four consecutive texels), each with its parent m1 (or itself at the top)
 #pragma unroll
-    for (int r = 0; r < 2; ++r)
+    for (int c = 0; c < 2; ++c)
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
+        for (int r = 0; r < 2; ++r) {
             const int x = x0 + c, y = y0 + r;
             if (x < W && y < H) {
                 const float2 par = top >= 1 ? m1 : p[r][c];
                 pyr[hiz_index(lay, 0, x, y)] = make_float4(p[r][c].x, p[r][c].y, par.x, par.y);
             }
         }
-    if (tile_levels < 1) return;
-    {
-        // level 1: its parent comes from the LDS pass below (or it is the top)
-        const int lx = x0 / 2, ly = y0 / 2;
-        if (lx < lay.w[1] && ly < lay.h[1]) {
-            const int64_t at = hiz_index(lay, 1, lx, ly);
-            put(pyr, at, m1);
-            if (top == 1) put_parent(pyr, at, m1);
+    // levels 1..tile_levels: texel (q1x >> (L - 1), q1y >> (L - 1)), written
+    // by the first lane of its group; its parent is the next level's pair,
+    // or its own at the top; level 5's parent comes from the pass above
+#pragma unroll
+    for (int L = 1; L <= kTileLevels; ++L) {
+        if (L > tile_levels) break;
+        const int low = (1 << (2 * (L - 1))) - 1;   // the lane bits within the group
+        const bool first = L < 5 ? (lane & low) == 0 : threadIdx.x == 0;
+        const int lx = q1x >> (L - 1), ly = q1y >> (L - 1);
+        if (first && lx < lay.w[L] && ly < lay.h[L]) {
+            const int64_t at = hiz_index(lay, L, lx, ly);
+            if (L < top) {
+                if (L < kTileLevels)
+                    pyr[at] = make_float4(m[L].x, m[L].y, m[L + 1].x, m[L + 1].y);
+                else
+                    put(pyr, at, m[L]);
+            } else {
+                pyr[at] = make_float4(m[L].x, m[L].y, m[L].x, m[L].y);
+            }
         }
-    }
-    lds[0][ty * 16 + tx] = m1;
-    int n = 16;  // current level's tile width in texels
-    int cur = 0;
-    for (int L = 2; L <= tile_levels; ++L) {
-        __syncthreads();
-        const int m = n / 2;
-        if (static_cast<int>(threadIdx.x) < m * m) {
-            const int a = threadIdx.x % m, b = threadIdx.x / m;
-            const float2* s = lds[cur];
-            const float2 v = mm(mm(s[(2 * b) * n + 2 * a], s[(2 * b) * n + 2 * a + 1]),
-                                mm(s[(2 * b + 1) * n + 2 * a], s[(2 * b + 1) * n + 2 * a + 1]));
-            lds[cur ^ 1][b * m + a] = v;
-            const int lx = blockIdx.x * (kTile >> L) + a, ly = blockIdx.y * (kTile >> L) + b;
-            if (lx < lay.w[L] && ly < lay.h[L]) put_level(pyr, lay, L, lx, ly, v);
-        }
-        cur ^= 1;
-        n = m;
     }
 }
 
