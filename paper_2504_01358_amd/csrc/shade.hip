@@ -355,13 +355,13 @@ __global__ __launch_bounds__(256) void trace_linear_kernel(const ShadeArgs a) {
 #define SSR_GEN_BATCH 3
 #endif
 #ifndef SSR_QUEUE_LOW
-#define SSR_QUEUE_LOW 64
+#define SSR_QUEUE_LOW 32
 #endif
 #ifndef SSR_REFILL_MIN
 #define SSR_REFILL_MIN 24
 #endif
 #ifndef SSR_STEP_UNROLL
-#define SSR_STEP_UNROLL 6
+#define SSR_STEP_UNROLL 5
 #endif
 #ifndef SSR_GUIDE_A
 #define SSR_GUIDE_A 85
@@ -383,9 +383,15 @@ constexpr int kStepUnroll = SSR_STEP_UNROLL;   // march iterations between idle 
 constexpr int kGuideWhole = SSR_GUIDE_A;       // percent of tiles handed out whole,
 constexpr int kGuideHalf = SSR_GUIDE_B;        //   up to this percent in halves,
 constexpr int kGuideDiv = SSR_GUIDE_DIV;       //   the rest in this many parts
-// the queue never holds more than kQueueLow - 1 + kGenBatch * 64 rays
-constexpr int kQueueCap = 256;
-static_assert(kQueueLow - 1 + kGenBatch * 64 <= kQueueCap, "ray queue too small");
+// the queue never holds more than kQueueLow - 1 + kGenBatch * 64 rays (28 B
+// of LDS each: 6.3 KB per wave at the defaults, so that 20 waves fit a CU)
+constexpr int kQueueCap = kQueueLow + kGenBatch * 64;
+
+// A queue slot in [0, 2 kQueueCap) wrapped into [0, kQueueCap) (the smaller
+// of p and p - kQueueCap as unsigned numbers).
+__device__ __forceinline__ int wrap_queue(int p) {
+    return static_cast<int>(min(static_cast<unsigned>(p), static_cast<unsigned>(p - kQueueCap)));
+}
 
 // The counter starts past the units the waves take first (unit = wave index),
 // so that the waves do not all queue on it at the start.
@@ -461,7 +467,7 @@ void trace_hiz_kernel(const ShadeArgs a) {
 
     int unit = blockIdx.x;      // unit being drawn (n_units or more: none left)
     set_unit(unit);
-    int qh = 0, qt = 0;         // queue head and tail (monotone; slots modulo kQueueCap)
+    int qh = 0, qn = 0;         // queue head (a slot) and length
     int nidle = 64;             // lanes without a ray
     HizRay r;
     int32_t* dst = nullptr;     // where the marching ray's hit code goes
@@ -475,7 +481,7 @@ void trace_hiz_kernel(const ShadeArgs a) {
     };
     for (;;) {
         // draw more rays while the queue runs low
-        if (unit < n_units && qt - qh < kQueueLow) {
+        if (unit < n_units && qn < kQueueLow) {
             asm volatile("" ::: "memory");
             const int i = (tile % tiles_x) * 8 + (lane & 7), j = (tile / tiles_x) * 8 + (lane >> 3);
             const bool inb = i < a.W && j < a.H;
@@ -508,7 +514,7 @@ void trace_hiz_kernel(const ShadeArgs a) {
                 }
                 const unsigned long long m = __ballot(queue);
                 if (queue) {
-                    const int pos = (qt + __popcll(m & below)) & (kQueueCap - 1);
+                    const int pos = wrap_queue(wrap_queue(qh + qn) + __popcll(m & below));
                     q_seg[pos] = make_float4(f.dPx, f.dPy, f.iz0, f.diz);
                     q_s1[pos] = f.s;
                     q_ray[pos] = make_uint2(pack_origin(i, j, f.ix, f.iy),
@@ -518,7 +524,7 @@ void trace_hiz_kernel(const ShadeArgs a) {
                     a.codes[code_index<TL>(a, i, j, k)] = code;
                     if (a.steps) a.steps[code_index<TL>(a, i, j, k)] = iters;
                 }
-                qt = __builtin_amdgcn_readfirstlane(qt + __popcll(m));
+                qn = __builtin_amdgcn_readfirstlane(qn + __popcll(m));
             }
             kk += g;
             if (kk == kend) {
@@ -529,12 +535,12 @@ void trace_hiz_kernel(const ShadeArgs a) {
             continue;
         }
         // refill idle lanes together once enough of them wait (or the queue is shorter)
-        const int rem = qt - qh;
+        const int rem = qn;
         if (rem > 0 && nidle >= min(kRefillMin, rem)) {
             const unsigned long long idle = __ballot(!active);
             const int rank = __popcll(idle & below);
             if (!active && rank < rem) {
-                const int pos = (qh + rank) & (kQueueCap - 1);
+                const int pos = wrap_queue(qh + rank);
                 const float4 gq = q_seg[pos];
                 const float s1 = q_s1[pos];
                 const uint2 ray = q_ray[pos];
@@ -549,17 +555,18 @@ void trace_hiz_kernel(const ShadeArgs a) {
                 dst = a.codes + queued_code_index<TL>(a, ri, rj, ray.y);
                 active = true;
             }
-            qh = __builtin_amdgcn_readfirstlane(qh + min(nidle, rem));
+            qh = __builtin_amdgcn_readfirstlane(wrap_queue(qh + min(nidle, rem)));
+            qn = __builtin_amdgcn_readfirstlane(rem - min(nidle, rem));
             nidle = __builtin_amdgcn_readfirstlane(__popcll(__ballot(!active)));
         }
         if (nidle == 64) {
-            if (unit >= n_units && qt == qh) break;
+            if (unit >= n_units && qn == 0) break;
             continue;
         }
         // march: one round when the queue wants more rays drawn, else until
         // enough lanes are idle to refill (all of them once nothing is queued)
-        const bool gen = unit < n_units && qt - qh < kQueueLow;
-        const int want = qt > qh ? min(kRefillMin, qt - qh) : 64;
+        const bool gen = unit < n_units && qn < kQueueLow;
+        const int want = qn > 0 ? min(kRefillMin, qn) : 64;
         // (kStepUnroll iterations between two counts of the idle lanes: the
         // count and the loop test cost as much as a fifth of an iteration)
         do {
