@@ -386,6 +386,9 @@ constexpr int kGuideDiv = SSR_GUIDE_DIV;       //   the rest in this many parts
 // the queue never holds more than kQueueLow - 1 + kGenBatch * 64 rays (28 B
 // of LDS each: 6.3 KB per wave at the defaults, so that 20 waves fit a CU)
 constexpr int kQueueCap = kQueueLow + kGenBatch * 64;
+// (wrap_queue takes slots below 2 kQueueCap: a head or tail slot plus fewer
+// than 64)
+static_assert(kGenBatch >= 1 && kQueueLow >= 1 && kQueueCap >= 64, "ray queue settings");
 
 // A queue slot in [0, 2 kQueueCap) wrapped into [0, kQueueCap) (the smaller
 // of p and p - kQueueCap as unsigned numbers).
