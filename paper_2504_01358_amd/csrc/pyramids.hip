@@ -216,7 +216,7 @@ __global__ __launch_bounds__(256) void hiz_tile_kernel(const float* __restrict__
     if (lane == 0) quad[wave] = m4;
     __syncthreads();
     const float2 m5 = mm(mm(quad[0], quad[1]), mm(quad[2], quad[3]));
-    const float2 m[6] = {p[0][0], m1, m2, m3, m4, m5};
+    const float2 m[kTileLevels + 1] = {p[0][0], m1, m2, m3, m4, m5};   // m[L]: level L (L >= 1)
     // level 0: the lane's four pixels (rows y0, y0 + 1 of the row pair y0 / 2:
     // four consecutive texels), each with its parent m1 (or itself at the top)
 #pragma unroll
@@ -236,7 +236,7 @@ __global__ __launch_bounds__(256) void hiz_tile_kernel(const float* __restrict__
     for (int L = 1; L <= kTileLevels; ++L) {
         if (L > tile_levels) break;
         const int low = (1 << (2 * (L - 1))) - 1;   // the lane bits within the group
-        const bool first = L < 5 ? (lane & low) == 0 : threadIdx.x == 0;
+        const bool first = L < kTileLevels ? (lane & low) == 0 : threadIdx.x == 0;
         const int lx = q1x >> (L - 1), ly = q1y >> (L - 1);
         if (first && lx < lay.w[L] && ly < lay.h[L]) {
             const int64_t at = hiz_index(lay, L, lx, ly);
