@@ -344,7 +344,8 @@ __global__ __launch_bounds__(256) void trace_linear_kernel(const ShadeArgs a) {
 //     once.  When a unit's samples are all drawn the wave takes the next;
 //   * march: lanes take rays from the queue, any lane any ray, and a lane
 //     whose ray ends takes the next one.  Idle lanes are refilled together
-//     once kRefillMin of them wait (or the queue is shorter).
+//     once kRefillMin of them wait (or the queue is shorter); a refilled
+//     lane first writes the code of the ray it marched before.
 // New rays are drawn while older ones are still marching, across tile
 // boundaries, so the lanes stay busy until the frame runs out of tiles.
 //
@@ -425,6 +426,10 @@ void trace_hiz_kernel(const ShadeArgs a) {
     __shared__ float4 q_seg[kQueueCap];     // queued rays: (dPx, dPy, iz0, diz),
     __shared__ float q_s1[kQueueCap];       //   segment parameter after the first iteration,
     __shared__ uint2 q_ray[kQueueCap];      //   packed origin and first step, code slot
+    // the code of a lane's ended ray, stored when the lane takes its next ray
+    // (or when the wave ends): one store per refill instead of a store in
+    // almost every march iteration
+    __shared__ int pend[64];
     const int lane = threadIdx.x;
     {
         // levels past the top (never reached) alias the top texel
@@ -475,10 +480,10 @@ void trace_hiz_kernel(const ShadeArgs a) {
     HizRay r;
     int32_t* dst = nullptr;     // where the marching ray's hit code goes
     bool active = false;
-    // a lane's ray ended: write its code (and iteration count)
+    // a lane's ray ended: keep its code (and write its iteration count)
     int wit = 0;                // the wave's march steps so far (see HizRay::deadline)
     auto finish = [&](bool hit, bool leave) {
-        *dst = hit ? r.iy * a.W + r.ix : (leave ? SSR_HIT_OFFSCREEN : SSR_HIT_CAP);
+        pend[lane] = hit ? r.iy * a.W + r.ix : (leave ? SSR_HIT_OFFSCREEN : SSR_HIT_CAP);
         if (a.steps) a.steps[dst - a.codes] = wit - r.deadline + a.max_steps;
         active = false;
     };
@@ -543,6 +548,7 @@ void trace_hiz_kernel(const ShadeArgs a) {
             const unsigned long long idle = __ballot(!active);
             const int rank = __popcll(idle & below);
             if (!active && rank < rem) {
+                if (dst) *dst = pend[lane];   // the code of the lane's previous ray
                 const int pos = wrap_queue(qh + rank);
                 const float4 gq = q_seg[pos];
                 const float s1 = q_s1[pos];
@@ -563,7 +569,10 @@ void trace_hiz_kernel(const ShadeArgs a) {
             nidle = __builtin_amdgcn_readfirstlane(__popcll(__ballot(!active)));
         }
         if (nidle == 64) {
-            if (unit >= n_units && qn == 0) break;
+            if (unit >= n_units && qn == 0) {
+                if (dst) *dst = pend[lane];
+                break;
+            }
             continue;
         }
         // march: one round when the queue wants more rays drawn, else until
