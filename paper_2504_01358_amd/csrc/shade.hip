@@ -412,6 +412,13 @@ __device__ __forceinline__ unsigned pack_origin(int i, int j, int nx, int ny) {
            (static_cast<unsigned>(j) << 16) | (static_cast<unsigned>(ny - j + 1) << 30);
 }
 
+// The number of lanes below this one whose bit is set in the wave mask m
+// (v_mbcnt: no per-lane mask kept in registers).
+__device__ __forceinline__ int lanes_below(unsigned long long m) {
+    return static_cast<int>(__builtin_amdgcn_mbcnt_hi(static_cast<unsigned>(m >> 32),
+                                                      __builtin_amdgcn_mbcnt_lo(static_cast<unsigned>(m), 0u)));
+}
+
 // Code index of a queued ray (see code_index).
 template <int TL>
 __device__ __forceinline__ int64_t queued_code_index(const ShadeArgs& a, int i, int j, unsigned slot) {
@@ -442,7 +449,6 @@ void trace_hiz_kernel(const ShadeArgs a) {
     const int tiles_x = (a.W + 7) / 8;
     const int n_tiles = tiles_x * ((a.H + 7) / 8);
     const int S = a.spp;
-    const unsigned long long below = (1ull << lane) - 1ull;
     // guided work units: whole tiles first, then the last tiles in chunks of
     // half and a quarter of their samples, so that the waves finish the
     // frame together (with whole tiles to the end, a wave that takes the
@@ -522,7 +528,7 @@ void trace_hiz_kernel(const ShadeArgs a) {
                 }
                 const unsigned long long m = __ballot(queue);
                 if (queue) {
-                    const int pos = wrap_queue(wrap_queue(qh + qn) + __popcll(m & below));
+                    const int pos = wrap_queue(wrap_queue(qh + qn) + lanes_below(m));
                     q_seg[pos] = make_float4(f.dPx, f.dPy, f.iz0, f.diz);
                     q_s1[pos] = f.s;
                     q_ray[pos] = make_uint2(pack_origin(i, j, f.ix, f.iy),
@@ -546,7 +552,7 @@ void trace_hiz_kernel(const ShadeArgs a) {
         const int rem = qn;
         if (rem > 0 && nidle >= min(kRefillMin, rem)) {
             const unsigned long long idle = __ballot(!active);
-            const int rank = __popcll(idle & below);
+            const int rank = lanes_below(idle);
             if (!active && rank < rem) {
                 if (dst) *dst = pend[lane];   // the code of the lane's previous ray
                 const int pos = wrap_queue(qh + rank);
