@@ -168,6 +168,23 @@ def test_c2_1080p_sampled_parity(ctx):
     _check(_cmp(g, ref, "c2-1080p"), g, ref)
 
 
+@pytest.mark.parametrize("dtype", ["f32", "f16"])
+def test_4k_sampled_parity(ctx, dtype):
+    """The largest resolution of the serving mix (3840x2160, 4 spp, Hi-Z;
+    FP32 and FP16 storage) in the benchmark's launch configuration: a deeper
+    pyramid and pixel coordinates near 2^12; the oracle, fed the values the
+    GPU read, shades a seeded sample of pixels one by one."""
+    sc = scenes.make_scene("c2", width=3840, height=2160, spp=4)
+    gpu, seen = run_gpu(ctx, sc.camera, gbuf_of(sc), sc.env, sc.params, dtype=dtype, tiled=True)
+    rng = np.random.default_rng(2160)
+    pix = rng.choice(sc.width * sc.height, 4096, replace=False)
+    ref = oracle.shade_pixels(sc.camera, seen, sc.env, sc.params, pix, sensitivity=DIR_EPS)
+    S = sc.params["spp"]
+    g = dict(out=gpu["out"].reshape(-1, 3)[pix], hits=gpu["hits"].reshape(-1, S)[pix],
+             steps=gpu["steps"].reshape(-1, S)[pix])
+    _check(_cmp(g, ref, f"4k-{dtype}"), g, ref)
+
+
 @pytest.mark.parametrize("dtype", ["f16", "bf16"])
 def test_reduced_precision_gbuffer(ctx, dtype):
     """FP16/BF16 G-buffers (depth FP32): parity with the oracle fed the same
