@@ -70,12 +70,100 @@ __global__ void env_down_kernel(const float4* __restrict__ src, float4* __restri
                          ((a.z + b.z) + (c.z + d.z)) * 0.25f, 0.0f);
 }
 
+// Box mean of four texels: the two of row 2y (a, b) and the two of row
+// 2y + 1 (c, d), summed in that order (the same arithmetic in every pass).
+__device__ __forceinline__ float4 box4(float4 a, float4 b, float4 c, float4 d) {
+    return make_float4(((a.x + b.x) + (c.x + d.x)) * 0.25f, ((a.y + b.y) + (c.y + d.y)) * 0.25f,
+                       ((a.z + b.z) + (c.z + d.z)) * 0.25f, 0.0f);
+}
+
+// Levels 0..5 of a 32 x 32 texel tile of the map (the map is at least 64 x 32,
+// a power of two in each direction, so tiles never cross its edge): each of
+// the 256 threads converts a 2 x 2 block and writes its level-1 mean, and
+// the 16 x 16 level-1 texels go through LDS for levels 2..5.  Every texel is
+// the same box mean of the same four values as in the level-by-level pass.
+constexpr int kEnvTile = 32;
+__global__ __launch_bounds__(256) void env_tile_kernel(const float* __restrict__ rgb,
+                                                       float4* __restrict__ mips, EnvLayout lay) {
+    __shared__ float4 lds[2][16 * 16];
+    const int W = lay.w[0];
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    const int x0 = blockIdx.x * kEnvTile + 2 * tx, y0 = blockIdx.y * kEnvTile + 2 * ty;
+    float4 t[2][2];
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const float* row = rgb + 3 * (static_cast<int64_t>(y0 + r) * W + x0);
+#pragma unroll
+        for (int c = 0; c < 2; ++c) t[r][c] = make_float4(row[3 * c], row[3 * c + 1], row[3 * c + 2], 0.0f);
+        float4* dst = mips + static_cast<int64_t>(y0 + r) * W + x0;
+        dst[0] = t[r][0];
+        dst[1] = t[r][1];
+    }
+    const float4 m1 = box4(t[0][0], t[0][1], t[1][0], t[1][1]);
+    mips[lay.offset[1] + static_cast<int64_t>(y0 / 2) * lay.w[1] + x0 / 2] = m1;
+    lds[0][ty * 16 + tx] = m1;
+    int n = 16, cur = 0;
+    for (int L = 2; L <= 5; ++L) {
+        __syncthreads();
+        const int m = n / 2;
+        if (static_cast<int>(threadIdx.x) < m * m) {
+            const int a = threadIdx.x % m, b = threadIdx.x / m;
+            const float4* src = lds[cur];
+            const float4 v = box4(src[(2 * b) * n + 2 * a], src[(2 * b) * n + 2 * a + 1],
+                                  src[(2 * b + 1) * n + 2 * a], src[(2 * b + 1) * n + 2 * a + 1]);
+            lds[cur ^ 1][b * m + a] = v;
+            const int lx = blockIdx.x * (kEnvTile >> L) + a, ly = blockIdx.y * (kEnvTile >> L) + b;
+            mips[lay.offset[L] + static_cast<int64_t>(ly) * lay.w[L] + lx] = v;
+        }
+        cur ^= 1;
+        n = m;
+    }
+}
+
+// The levels from `first` up, in one workgroup, through LDS (level first-1
+// holds at most kEnvTopTexels texels).
+constexpr int kEnvTopTexels = 2048;
+__global__ __launch_bounds__(1024) void env_top_kernel(float4* __restrict__ mips, EnvLayout lay,
+                                                       int first) {
+    __shared__ float4 buf[kEnvTopTexels + kEnvTopTexels / 4];
+    const int sw0 = lay.w[first - 1], sh0 = lay.h[first - 1];
+    float4* a = buf;
+    float4* b = buf + sw0 * sh0;
+    for (int i = threadIdx.x; i < sw0 * sh0; i += blockDim.x) a[i] = mips[lay.offset[first - 1] + i];
+    for (int L = first; L < lay.levels; ++L) {
+        __syncthreads();
+        const int sw = lay.w[L - 1], dw = lay.w[L], dh = lay.h[L];
+        for (int i = threadIdx.x; i < dw * dh; i += blockDim.x) {
+            const int x = i % dw, y = i / dw;
+            const float4 v = box4(a[(2 * y) * sw + 2 * x], a[(2 * y) * sw + 2 * x + 1],
+                                  a[(2 * y + 1) * sw + 2 * x], a[(2 * y + 1) * sw + 2 * x + 1]);
+            b[i] = v;
+            mips[lay.offset[L] + i] = v;
+        }
+        float4* tmp = a;
+        a = b;
+        b = tmp;
+    }
+}
+
 hipError_t launch_env_mips(const float* rgb, const EnvLayout& lay, float4* mips,
                            hipStream_t stream) {
-    const int n0 = lay.w[0] * lay.h[0];
-    hipLaunchKernelGGL(env_level0_kernel, dim3((n0 + 255) / 256), dim3(256), 0, stream, rgb, mips,
-                       n0);
-    for (int k = 1; k < lay.levels; ++k) {
+    int next = 1;   // the first level the passes below still have to build
+    if (lay.h[0] >= kEnvTile) {
+        // levels 0..5 by tiles, then the top in one workgroup when it is small
+        hipLaunchKernelGGL(env_tile_kernel, dim3(lay.w[0] / kEnvTile, lay.h[0] / kEnvTile), dim3(256),
+                           0, stream, rgb, mips, lay);
+        next = 6;
+        if (next < lay.levels && lay.w[next - 1] * lay.h[next - 1] <= kEnvTopTexels) {
+            hipLaunchKernelGGL(env_top_kernel, dim3(1), dim3(1024), 0, stream, mips, lay, next);
+            next = lay.levels;
+        }
+    } else {
+        const int n0 = lay.w[0] * lay.h[0];
+        hipLaunchKernelGGL(env_level0_kernel, dim3((n0 + 255) / 256), dim3(256), 0, stream, rgb,
+                           mips, n0);
+    }
+    for (int k = next; k < lay.levels; ++k) {
         const int n = lay.w[k] * lay.h[k];
         hipLaunchKernelGGL(env_down_kernel, dim3((n + 255) / 256), dim3(256), 0, stream,
                            mips + lay.offset[k - 1], mips + lay.offset[k], lay.w[k - 1], lay.w[k],
