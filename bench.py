@@ -155,25 +155,51 @@ def kernel_sources_digest():
     return h.hexdigest()
 
 
-def measured_traffic():
-    """HBM bytes per launch of the shading kernel from the committed counter
-    summary, or None when it is absent or was taken from other sources."""
+# the "name = value" figures of the counter summary that the line reports
+PROFILE_FIGURES = ("traffic_bytes_per_launch", "l2_hit_rate", "valu_busy", "valu_lane_utilisation")
+
+
+def profile_figures():
+    """The figures of the committed counter summary (HBM bytes per launch of
+    the shading kernel, its L2 hit rate, VALU busy share and lane utilisation),
+    or {} when the summary is absent or was taken from other sources."""
     try:
         with open(COUNTER_SUMMARY) as f:
             text = f.read()
     except OSError:
-        return None
+        return {}
     vals = {}
     for ln in text.splitlines():
-        if "=" in ln and ln.strip().startswith(("traffic_bytes_per_launch", "sources_sha256")):
+        if "=" in ln and ln.strip().startswith(PROFILE_FIGURES + ("sources_sha256",)):
             k, v = ln.strip().strip("`").split("=", 1)
             vals[k.strip()] = v.strip().strip("`")
-    if vals.get("sources_sha256") != kernel_sources_digest():
+    if vals.pop("sources_sha256", None) != kernel_sources_digest():
+        return {}
+    out = {}
+    for k, v in vals.items():
+        try:
+            out[k] = float(v)
+        except ValueError:
+            pass
+    return out
+
+
+def measured_traffic():
+    """HBM bytes per launch of the shading kernel from the committed counter
+    summary, or None when it is absent or was taken from other sources."""
+    return profile_figures().get("traffic_bytes_per_launch")
+
+
+def measured_counters():
+    """L2 hit rate, VALU busy share and lane utilisation of the shading kernel
+    from the committed counter summary (None under the same rule as the
+    traffic)."""
+    f = profile_figures()
+    keys = ("l2_hit_rate", "valu_busy", "valu_lane_utilisation")
+    if not all(k in f for k in keys):
         return None
-    try:
-        return float(vals["traffic_bytes_per_launch"])
-    except (KeyError, ValueError):
-        return None
+    return dict({k: f[k] for k in keys},
+                source=os.path.relpath(COUNTER_SUMMARY, ROOT))
 
 
 def time_gpu(ctx, scene, dtype, steps, warmup, dev, mips):
@@ -660,6 +686,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": B / trace_s / 1e9, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": B / trace_s / 1e9 / HBM_PEAK_GBS,
                      "traffic": measured_traffic() if args.config == "c2" else None,
+                     "counters": measured_counters() if args.config == "c2" else None,
                      "kernel": "trace_hiz_kernel<f32>", "kernel_ms": r32["trace_ms"],
                      "algorithmic_bytes": B,
                      "bytes_model": "P (B_g + 12 + 16/3) + sum over samples (4 n_iter + B_r), "

@@ -69,13 +69,21 @@ def test_error_report_by_hand():
 
 def test_traffic_figure_needs_matching_sources(tmp_path, monkeypatch):
     good = tmp_path / "summary.md"
-    good.write_text("traffic_bytes_per_launch = 123\n\nsources_sha256 = "
+    good.write_text("traffic_bytes_per_launch = 123\n\nl2_hit_rate = 0.5\n\nvalu_busy = 0.25\n\n"
+                    "valu_lane_utilisation = 0.75\n\nsources_sha256 = "
                     + bench.kernel_sources_digest() + "\n")
     monkeypatch.setattr(bench, "COUNTER_SUMMARY", str(good))
     assert bench.measured_traffic() == 123
+    c = bench.measured_counters()
+    assert (c["l2_hit_rate"], c["valu_busy"], c["valu_lane_utilisation"]) == (0.5, 0.25, 0.75)
+    partial = tmp_path / "partial.md"
+    partial.write_text("traffic_bytes_per_launch = 123\n\nsources_sha256 = "
+                       + bench.kernel_sources_digest() + "\n")
+    monkeypatch.setattr(bench, "COUNTER_SUMMARY", str(partial))
+    assert bench.measured_traffic() == 123 and bench.measured_counters() is None
     stale = tmp_path / "stale.md"
     stale.write_text("traffic_bytes_per_launch = 123\n\nsources_sha256 = 00\n")
     monkeypatch.setattr(bench, "COUNTER_SUMMARY", str(stale))
-    assert bench.measured_traffic() is None
+    assert bench.measured_traffic() is None and bench.measured_counters() is None
     monkeypatch.setattr(bench, "COUNTER_SUMMARY", str(tmp_path / "absent.md"))
     assert bench.measured_traffic() is None
