@@ -98,13 +98,18 @@ def _agree(got, want, label, rel=2e-3, frac=0.99):
     return worst
 
 
-@pytest.mark.parametrize("flags", [0, 1, 2])
-def test_pixel_gradients_match_oracle(ctx, flags):
+@pytest.mark.parametrize("flags,seed,frame", [(0, None, 0), (1, None, 0), (2, None, 0),
+                                              (0, 0x9E3779B97F4A7C15, 3)])
+def test_pixel_gradients_match_oracle(ctx, flags, seed, frame):
     """All eight per-pixel derivatives of every pixel of a frame with the 1080p
     scene's object mix and high-contrast environment, against central
-    differences of the FP64 forward with the same hit codes."""
+    differences of the FP64 forward with the same hit codes (also with a
+    64-bit seed whose high word is set and a nonzero frame index: the adjoint
+    draws the forward's samples)."""
     sc = _interior(scenes.make_scene("c2", seed=61, width=48, height=32, spp=4), 1)
     sc.params["flags"] = flags
+    if seed is not None:
+        sc.params.update(seed=seed, frame=frame)
     dev = torch.device("cuda", 0)
     t = _up(sc, dev)
     hits, h = _oracle_hits(sc, dev)
@@ -116,7 +121,7 @@ def test_pixel_gradients_match_oracle(ctx, flags):
                              g_out.reshape(-1, 3))
     gpu = np.concatenate([got["g_nr"].reshape(-1, 4), got["g_am"].reshape(-1, 4)], axis=1)
     assert np.isfinite(gpu).all()
-    _agree(gpu, want, f"pixel grads flags={flags}")
+    _agree(gpu, want, f"pixel grads flags={flags} seed={seed} frame={frame}")
 
 
 def test_env_and_radiance_gradients_match_oracle(ctx):

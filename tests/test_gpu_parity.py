@@ -153,6 +153,28 @@ def test_ragged_multi_tile_parity(ctx, march, tiled):
     _check(_cmp(gpu, ref, f"ragged-{march}{'-tiled' if tiled else ''}"), gpu, ref)
 
 
+@pytest.mark.parametrize("march", ["linear", "hiz"])
+def test_seed_high_word_and_frame_index(ctx, march):
+    """The Philox key is (seed mod 2^32, seed >> 32) and the counter carries
+    the frame index: a 64-bit seed whose high word is set and a nonzero frame
+    reach the kernels intact (parity with the oracle), and changing only the
+    high word of the seed, or only the frame, changes the sample draws."""
+    kw = dict(width=96, height=64, spp=4, march=march)
+    if march == "linear":
+        kw.update(max_steps=32, max_dist=4.0)
+    sc = scenes.make_scene("c2", seed=29, **kw)
+    seed = 0x9E3779B97F4A7C15
+    p = dict(sc.params, seed=seed, frame=7)
+    gpu, seen = run_gpu(ctx, sc.camera, gbuf_of(sc), sc.env, p)
+    ref = oracle_frame(sc.camera, seen, sc.env, p)
+    _check(_cmp(gpu, ref, f"seed-hi-frame7-{march}"), gpu, ref)
+    for other in (dict(p, seed=seed & 0xFFFFFFFF), dict(p, frame=0)):
+        g2, _ = run_gpu(ctx, sc.camera, gbuf_of(sc), sc.env, other)
+        marched = ~np.isin(gpu["hits"], NO_MARCH)
+        assert (g2["hits"] != gpu["hits"])[marched].mean() > 0.05
+        assert not np.array_equal(g2["out"], gpu["out"])
+
+
 def test_c2_1080p_sampled_parity(ctx):
     """The headline workload at full size (1920x1080, 16 spp, Hi-Z, FP32) in
     the launch configuration the bench times; the oracle shades a seeded
