@@ -224,6 +224,33 @@ def test_env_bilinear_texel_centres_and_uniform():
     assert np.abs(env.trilinear(mips, dd, rng.uniform(0, 3, 1000)) - 3.25).max() < 1e-14
 
 
+def test_env_bilinear_equals_scipy_linear_interpolation():
+    """Between texel centres: the lookup is linear interpolation at texel
+    coordinates (u W - 1/2, v H - 1/2), wrapping in u and clamping in v,
+    which SciPy's order-1 map_coordinates gives on the map padded by one
+    wrapped column each side and one repeated row above and below.  Random
+    directions, the poles' rows and the seam included."""
+    from scipy import ndimage
+    rng = np.random.default_rng(41)
+    he, we = 16, 32
+    img = np.exp(rng.normal(0, 1, (he, we, 3)))
+    d = brdf.normalize(rng.normal(size=(4000, 3)))
+    # directions near the poles and on both sides of the seam (u near 0 and 1)
+    near_pole = brdf.normalize(np.stack([rng.normal(size=200) * 0.05, np.sign(rng.normal(size=200)),
+                                         rng.normal(size=200) * 0.05], axis=1))
+    seam = brdf.normalize(np.stack([rng.normal(size=200) * 1e-3, rng.normal(size=200),
+                                    np.full(200, 1.0)], axis=1))
+    d = np.concatenate([d, near_pole, seam])
+    u, v = env.dir_to_uv(d)
+    padded = np.pad(np.pad(img, ((0, 0), (1, 1), (0, 0)), mode="wrap"),
+                    ((1, 1), (0, 0), (0, 0)), mode="edge")
+    coords = [v * he - 0.5 + 1.0, u * we - 0.5 + 1.0]
+    want = np.stack([ndimage.map_coordinates(padded[..., c], coords, order=1, mode="nearest")
+                     for c in range(3)], axis=1)
+    got = env.bilinear(img, d)
+    assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max()
+
+
 def test_env_mips_are_block_means():
     rng = np.random.default_rng(6)
     img = np.exp(rng.normal(0, 2, (32, 64, 3)))
