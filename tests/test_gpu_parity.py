@@ -175,11 +175,15 @@ def test_seed_high_word_and_frame_index(ctx, march):
         assert not np.array_equal(g2["out"], gpu["out"])
 
 
-def test_c2_1080p_sampled_parity(ctx):
+@pytest.mark.parametrize("scene_seed", [None, 77])
+def test_c2_1080p_sampled_parity(ctx, scene_seed):
     """The headline workload at full size (1920x1080, 16 spp, Hi-Z, FP32) in
     the launch configuration the bench times; the oracle shades a seeded
-    sample of pixels one by one."""
-    sc = scenes.make_scene("c2")
+    sample of pixels one by one.  Also a second scene of the same recipe
+    (other object placement, materials and environment; Philox seed 77)."""
+    sc = scenes.make_scene("c2") if scene_seed is None else scenes.make_scene("c2", seed=scene_seed)
+    if scene_seed is not None:
+        sc.params["seed"] = scene_seed
     gpu, seen = run_gpu(ctx, sc.camera, gbuf_of(sc), sc.env, sc.params, tiled=True)
     rng = np.random.default_rng(123)
     pix = rng.choice(sc.width * sc.height, 4096, replace=False)
@@ -187,7 +191,7 @@ def test_c2_1080p_sampled_parity(ctx):
     S = sc.params["spp"]
     g = dict(out=gpu["out"].reshape(-1, 3)[pix], hits=gpu["hits"].reshape(-1, S)[pix],
              steps=gpu["steps"].reshape(-1, S)[pix])
-    _check(_cmp(g, ref, "c2-1080p"), g, ref)
+    _check(_cmp(g, ref, f"c2-1080p-scene{scene_seed}"), g, ref)
 
 
 @pytest.mark.parametrize("dtype", ["f32", "f16"])
