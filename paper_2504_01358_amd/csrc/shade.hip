@@ -14,6 +14,8 @@
 // point (linear) or a pixel crossing (hierarchical) hits when the ray lies in
 // the slab [D, D + thickness] behind the depth buffer after having been in
 // front of it at some earlier point outside the origin pixel.
+#include <algorithm>
+
 #include "shading.h"
 
 namespace ssr {
@@ -426,9 +428,13 @@ __device__ __forceinline__ int64_t queued_code_index(const ShadeArgs& a, int i, 
     return code_index<TL>(a, i, j, static_cast<int>(slot));
 }
 
-template <int DT, int TL>
+// SPLIT: the frame has fewer tiles than resident waves, and every tile is
+// handed out in `split` parts of its samples (then halves and quarters of
+// those), so that all waves get work; otherwise whole tiles first (split is
+// then unused).
+template <int DT, int TL, bool SPLIT>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(SSR_WAVES_PER_EU, 8)))
-void trace_hiz_kernel(const ShadeArgs a) {
+void trace_hiz_kernel(const ShadeArgs a, int split) {
     __shared__ int2 lvl[kMaxLevels];
     __shared__ float4 q_seg[kQueueCap];     // queued rays: (dPx, dPy, iz0, diz),
     __shared__ float q_s1[kQueueCap];       //   segment parameter after the first iteration,
@@ -454,11 +460,14 @@ void trace_hiz_kernel(const ShadeArgs a) {
     // frame together (with whole tiles to the end, a wave that takes the
     // last tile marches ~0.3 ms after others ran dry) without many more
     // trips to the shared counter (units of one or two samples contend on it)
-    const int c1 = max(1, S / 2), c2 = max(1, S / kGuideDiv);   // chunk sizes of the tail
-    const int n1 = (n_tiles * kGuideWhole) / 100;              // whole tiles
+    // (SPLIT: units of c0 = S / split samples come first, k0 of them per tile)
+    const int c0 = SPLIT ? max(1, S / split) : S;
+    const int k0 = SPLIT ? (S + c0 - 1) / c0 : 1;
+    const int c1 = max(1, c0 / 2), c2 = max(1, c0 / kGuideDiv);  // chunk sizes of the tail
+    const int n1 = (n_tiles * kGuideWhole) / 100;              // tiles in units of c0
     const int n2 = (n_tiles * kGuideHalf) / 100;               // tiles in chunks of c1
     const int k1 = (S + c1 - 1) / c1, k2 = (S + c2 - 1) / c2;
-    const int u1 = n1, u2 = u1 + (n2 - n1) * k1, n_units = u2 + (n_tiles - n2) * k2;
+    const int u1 = n1 * k0, u2 = u1 + (n2 - n1) * k1, n_units = u2 + (n_tiles - n2) * k2;
     auto next_unit = [&]() {
         int t = 0;
         if (lane == 0) t = atomicAdd(a.tile_counter, 1);
@@ -468,7 +477,11 @@ void trace_hiz_kernel(const ShadeArgs a) {
     int tile = 0, kk = 0, kend = 0;
     auto set_unit = [&](int u) {
         if (u < u1) {
-            tile = u; kk = 0; kend = S;
+            if (SPLIT) {
+                tile = u / k0; kk = (u % k0) * c0; kend = min(kk + c0, S);
+            } else {
+                tile = u; kk = 0; kend = S;
+            }
         } else if (u < u2) {
             const int v = u - u1;
             tile = n1 + v / k1; kk = (v % k1) * c1; kend = min(kk + c1, S);
@@ -659,17 +672,50 @@ struct TraceLinearK {
 };
 template <int DT, int TL>
 struct TraceHizK {
-    static const void* fn() { return reinterpret_cast<const void*>(&trace_hiz_kernel<DT, TL>); }
+    static const void* fn() { return reinterpret_cast<const void*>(&trace_hiz_kernel<DT, TL, false>); }
+};
+template <int DT, int TL>
+struct TraceHizSplitK {
+    static const void* fn() { return reinterpret_cast<const void*>(&trace_hiz_kernel<DT, TL, true>); }
 };
 template <int DT, int TL>
 struct ResolveK {
     static const void* fn() { return reinterpret_cast<const void*>(&resolve_kernel<DT, TL>); }
 };
 
-int trace_grid(int cu_count, int W, int H) {
+#ifndef SSR_SPLIT_UNITS
+#define SSR_SPLIT_UNITS 4
+#endif
+// A frame with fewer tiles than resident waves splits each tile's samples
+// into `split` parts (a power of two) until there are about kSplitUnits
+// units per resident wave, keeping at least four samples in a part (units
+// of one or two samples cost more in counter trips and pixel set-ups than
+// they gain; a frame with more tiles than waves measured slower split).
+// Returns 1 when the tiles are not split.
+constexpr int kSplitUnits = SSR_SPLIT_UNITS;
+int trace_split(int cu_count, int W, int H, int S) {
+    const int64_t n_tiles = static_cast<int64_t>((W + 7) / 8) * ((H + 7) / 8);
+    const int64_t resident = static_cast<int64_t>(cu_count) * 4 * kTraceWavesPerEU;
+    int f = 1;
+    if (n_tiles >= resident) return f;
+    while (S / (2 * f) >= 4 && n_tiles * f < kSplitUnits * resident) f *= 2;
+    return f;
+}
+
+// One persistent wave per unit, up to the resident count (the unit count as
+// the kernel computes it).
+int trace_grid(int cu_count, int W, int H, int S, int split) {
     const int n_tiles = ((W + 7) / 8) * ((H + 7) / 8);
+    int n_units = n_tiles;
+    if (split > 1) {
+        const int c0 = std::max(1, S / split), k0 = (S + c0 - 1) / c0;
+        const int c1 = std::max(1, c0 / 2), c2 = std::max(1, c0 / kGuideDiv);
+        const int n1 = (n_tiles * kGuideWhole) / 100, n2 = (n_tiles * kGuideHalf) / 100;
+        const int k1 = (S + c1 - 1) / c1, k2 = (S + c2 - 1) / c2;
+        n_units = n1 * k0 + (n2 - n1) * k1 + (n_tiles - n2) * k2;
+    }
     const int resident = cu_count * 4 * kTraceWavesPerEU;
-    return n_tiles < resident ? n_tiles : resident;
+    return n_units < resident ? n_units : resident;
 }
 
 void plan_trace(const ShadeArgs& args, int dtype, int march, int cu_count, Plan& plan) {
@@ -679,11 +725,15 @@ void plan_trace(const ShadeArgs& args, int dtype, int march, int cu_count, Plan&
         plan.add(pick<TraceLinearK>(dtype, tiled), grid, dim3(256)).arg(args);
         return;
     }
-    const dim3 grid(trace_grid(cu_count, args.W, args.H));
+    const int split = trace_split(cu_count, args.W, args.H, args.spp);
+    const dim3 grid(trace_grid(cu_count, args.W, args.H, args.spp, split));
     Launch& r = plan.add(reinterpret_cast<const void*>(&reset_counter_kernel), dim3(1), dim3(1));
     r.arg(args.tile_counter);
     r.arg(static_cast<int>(grid.x));
-    plan.add(pick<TraceHizK>(dtype, tiled), grid, dim3(64)).arg(args);
+    Launch& t = plan.add(split > 1 ? pick<TraceHizSplitK>(dtype, tiled) : pick<TraceHizK>(dtype, tiled),
+                         grid, dim3(64));
+    t.arg(args);
+    t.arg(split);
 }
 
 void plan_resolve(const ShadeArgs& args, int dtype, Plan& plan) {
