@@ -116,9 +116,13 @@ hipError_t run_plan(Plan& plan, hipStream_t stream);
 
 // The launches of the pyramid build, the trace (work counter reset, trace)
 // and the resolve, appended to `plan` (the launchers below run exactly these).
+// `overlapped`: the frame shares the device with other frames (a serving
+// session), so the trace splits its tiles only when it has fewer of them
+// than resident waves.
 void plan_hiz(const float* depth, const HizLayout& lay, float thickness, float4* pyramid,
               Plan& plan);
-void plan_trace(const ShadeArgs& args, int dtype, int march, int cu_count, Plan& plan);
+void plan_trace(const ShadeArgs& args, int dtype, int march, int cu_count, Plan& plan,
+                bool overlapped = false);
 void plan_resolve(const ShadeArgs& args, int dtype, Plan& plan);
 
 hipError_t launch_env_mips(const float* rgb, const EnvLayout& lay, float4* mips,

@@ -211,7 +211,7 @@ int ssr_session::launch(const ssr::serve::Admitted& ad) {
         ssr::plan_hiz(sc.depth, hl, p.thickness, hiz, *plan);
         a.hiz = hiz;
     }
-    ssr::plan_trace(a, sc.dtype, p.march, cu_count, *plan);
+    ssr::plan_trace(a, sc.dtype, p.march, cu_count, *plan, /*overlapped=*/true);
     ssr::plan_resolve(a, sc.dtype, *plan);
     if (cfg.flags & SSR_SESSION_DIRECT) {
         if (ssr::run_plan(*plan, s) != hipSuccess) return SSR_E_HIP;

@@ -686,19 +686,23 @@ struct ResolveK {
 #ifndef SSR_SPLIT_UNITS
 #define SSR_SPLIT_UNITS 4
 #endif
-// A frame with fewer tiles than resident waves splits each tile's samples
+// A frame with few tiles for the resident waves splits each tile's samples
 // into `split` parts (a power of two) until there are about kSplitUnits
-// units per resident wave, keeping at least four samples in a part (units
-// of one or two samples cost more in counter trips and pixel set-ups than
-// they gain; a frame with more tiles than waves measured slower split).
+// units per resident wave: with fewer tiles than waves, keeping at least
+// four samples in a part; with up to three tiles per wave, at least eight
+// (units of one or two samples cost more in counter trips and pixel
+// set-ups than they gain, and a draw of three samples then one wastes most
+// of a round).  A frame that shares the device with others is split only in
+// the first case: the other frames fill the waves its tail leaves idle.
 // Returns 1 when the tiles are not split.
 constexpr int kSplitUnits = SSR_SPLIT_UNITS;
-int trace_split(int cu_count, int W, int H, int S) {
+int trace_split(int cu_count, int W, int H, int S, bool overlapped) {
     const int64_t n_tiles = static_cast<int64_t>((W + 7) / 8) * ((H + 7) / 8);
     const int64_t resident = static_cast<int64_t>(cu_count) * 4 * kTraceWavesPerEU;
     int f = 1;
-    if (n_tiles >= resident) return f;
-    while (S / (2 * f) >= 4 && n_tiles * f < kSplitUnits * resident) f *= 2;
+    if (n_tiles >= (overlapped ? 1 : 3) * resident) return f;
+    const int min_part = n_tiles < resident ? 4 : 8;
+    while (S / (2 * f) >= min_part && n_tiles * f < kSplitUnits * resident) f *= 2;
     return f;
 }
 
@@ -718,14 +722,15 @@ int trace_grid(int cu_count, int W, int H, int S, int split) {
     return n_units < resident ? n_units : resident;
 }
 
-void plan_trace(const ShadeArgs& args, int dtype, int march, int cu_count, Plan& plan) {
+void plan_trace(const ShadeArgs& args, int dtype, int march, int cu_count, Plan& plan,
+                bool overlapped) {
     const bool tiled = (args.flags & SSR_CODES_TILED) != 0;
     if (march == SSR_MARCH_LINEAR) {
         const dim3 grid(((args.W + 15) / 16) * ((args.H + 15) / 16));
         plan.add(pick<TraceLinearK>(dtype, tiled), grid, dim3(256)).arg(args);
         return;
     }
-    const int split = trace_split(cu_count, args.W, args.H, args.spp);
+    const int split = trace_split(cu_count, args.W, args.H, args.spp, overlapped);
     const dim3 grid(trace_grid(cu_count, args.W, args.H, args.spp, split));
     Launch& r = plan.add(reinterpret_cast<const void*>(&reset_counter_kernel), dim3(1), dim3(1));
     r.arg(args.tile_counter);
