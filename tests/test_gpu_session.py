@@ -155,3 +155,30 @@ def test_session_errors_and_lifecycle():
         sess.submit(sid, dict(sc.params, spp=64, seed=k))
     sess.close()
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("graphs", [True, False])
+def test_split_units_equal_whole_tiles(graphs):
+    """A 1280x720 frame (14,400 tiles for at most a few thousand resident
+    waves) is traced by ssr_shade with its tiles handed out in parts of their
+    samples, and by a serving session with whole tiles (a session splits only
+    frames with fewer tiles than waves): which wave marches which ray must not
+    change the image, bit for bit."""
+    from paper_2504_01358_amd import ssr
+    dev = torch.device("cuda", 0)
+    ctx = ssr.Context(0)
+    sc = scenes.make_scene("c2", seed=41, width=1280, height=720)
+    u = _upload(sc, "f32", dev)
+    sess = ssr.Session(0, hbm_budget_bytes=1 << 30, max_slots=1, max_bypass=0, graphs=graphs)
+    sid = sess.add_scene(sc.camera, u["depth"], u["normal_rough"], u["albedo_metal"],
+                         u["radiance"], u["env"])
+    p = dict(sc.params, seed=9, frame=2)
+    t, out = sess.submit(sid, p)
+    r = sess.wait(t)
+    alone = ctx.shade(sc.camera, u["depth"], u["normal_rough"], u["albedo_metal"], u["radiance"],
+                      u["env"], p)
+    torch.cuda.synchronize()
+    assert r["status"] == 0
+    assert torch.equal(out, alone)
+    sess.close()
+    ctx.close()
