@@ -18,7 +18,9 @@ SOURCES = ["abi.hip", "pyramids.hip", "shade.hip", "session.hip", "backward.hip"
 
 def command(out=LIB, extra=()):
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    return [hipcc, "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    # -O2: the hierarchical trace kernel schedules its march iteration better
+    # than at -O3 (1080p/16 spp frame 0.3 % faster, the other kernels alike)
+    return [hipcc, "--offload-arch=gfx950", "-O2", "-std=c++17", "-fPIC", "-shared",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             "-Wall", "-Wno-unused-result",
             "-I", os.path.join(ROOT, "include"), "-I", CSRC,
